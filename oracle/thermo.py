@@ -1,0 +1,269 @@
+"""Bulk thermodynamics of the van der Waals mixture free energy (oracle side).
+
+TEST INFRASTRUCTURE ONLY: used by the test suite to pin the lattice Boltzmann
+oracle and the GPU library against quantities the paper fixes independently of
+any lattice update.  Shares no code with the GPU library.
+
+Notation follows Sec. II of the paper: densities rho^c, kT = theta, attraction
+a^{cc'}, excluded volume b^c, packing eta = sum_c b^c rho^c.
+
+Contents
+  critical_point           Eqs. tetcr, rhocr, pcr
+  two_component_params     the (theta_cr^A, theta_cr^B, rho_cr^B, nu) mapping of
+                           Sec. VI.A with the geometric mixing rule of Eq.
+                           vdwConstantAB (read as a = 9 theta_cr / (8 rho_cr),
+                           which is what Eqs. tetcr/rhocr give)
+  vks_parameters           van Konynenburg-Scott xi, zeta, Lambda (Sec. VI.A)
+  free_energy_density      bulk part of Eq. continuousFreeEnergy
+  chemical_potential       d f / d rho^c (including the +kT constant)
+  pressure                 bulk pressure of Sec. II
+  hessian                  the 2x2 (CxC) Hessian of Sec. VI.A
+  maxwell_single           liquid-gas coexistence of one component
+  coexistence_two_phase    common tangent between two bulk phases (Newton)
+  minimize_three_phase     the quasi-brute-force direct search of Appendix A
+  gamma_from_width_rule    gamma_mu from Eq. kappaGammaMuRelation
+"""
+from __future__ import annotations
+
+import numpy as np
+
+THETA_LB = 1.0 / 3.0
+
+
+def critical_point(a: float, b: float):
+    """(kT_cr, rho_cr, p_cr) of one van der Waals component (Eqs. tetcr, rhocr, pcr)."""
+    return 8.0 * a / (27.0 * b), 1.0 / (3.0 * b), a / (27.0 * b * b)
+
+
+def two_component_params(theta_cr_a: float, theta_cr_b: float, rho_cr_b: float, nu: float, rho_cr_a: float = 1.0):
+    """a^{cc'} (2x2) and b^c from critical temperatures/densities (Sec. VI.A).
+
+    Inverting Eqs. tetcr and rhocr gives b = 1/(3 rho_cr) and
+    a = 27 b theta_cr / 8 = 9 theta_cr / (8 rho_cr).  The cross term follows
+    the geometric mixing rule a^{AB} = nu sqrt(a^A a^B) (Eq. vdwConstantAB).
+    """
+    aA = 9.0 * theta_cr_a / (8.0 * rho_cr_a)
+    aB = 9.0 * theta_cr_b / (8.0 * rho_cr_b)
+    bA = 1.0 / (3.0 * rho_cr_a)
+    bB = 1.0 / (3.0 * rho_cr_b)
+    aAB = nu * np.sqrt(aA * aB)
+    return np.array([[aA, aAB], [aAB, aB]]), np.array([bA, bB])
+
+
+def vks_parameters(a: np.ndarray, b: np.ndarray):
+    """(xi, zeta, Lambda) of van Konynenburg and Scott for a binary mixture (Sec. VI.A)."""
+    pa = a[0, 0] / b[0] ** 2
+    pb = a[1, 1] / b[1] ** 2
+    xi = (b[1] - b[0]) / (b[0] + b[1])
+    zeta = (pb - pa) / (pa + pb)
+    lam = (pa - 2.0 * a[0, 1] / (b[0] * b[1]) + pb) / (pa + pb)
+    return xi, zeta, lam
+
+
+def _eta(rho, b):
+    return float(np.dot(b, rho))
+
+
+def free_energy_density(rho, kT, a, b):
+    """f(rho) = sum_c rho^c kT ln(rho^c/(1-eta)) - sum_{cc'} a^{cc'} rho^c rho^c'."""
+    rho = np.asarray(rho, dtype=float)
+    eta = _eta(rho, b)
+    return float(np.sum(rho * kT * np.log(rho / (1.0 - eta))) - rho @ a @ rho)
+
+
+def chemical_potential(rho, kT, a, b):
+    """Full bulk chemical potential d f / d rho^c (keeps the +kT constant)."""
+    rho = np.asarray(rho, dtype=float)
+    eta = _eta(rho, b)
+    tot = rho.sum()
+    return kT * (np.log(rho / (1.0 - eta)) + 1.0 + b * tot / (1.0 - eta)) - 2.0 * (a @ rho)
+
+
+def pressure(rho, kT, a, b):
+    """Bulk pressure p = sum_c rho^c kT/(1-eta) - sum a rho rho (Sec. II)."""
+    rho = np.asarray(rho, dtype=float)
+    eta = _eta(rho, b)
+    return float(rho.sum() * kT / (1.0 - eta) - rho @ a @ rho)
+
+
+def hessian(rho, kT, a, b):
+    """H_cd = d^2 f / d rho^c d rho^d of the bulk free-energy density."""
+    rho = np.asarray(rho, dtype=float)
+    b = np.asarray(b, dtype=float)
+    eta = _eta(rho, b)
+    tot = rho.sum()
+    g = 1.0 - eta
+    H = kT * (np.diag(1.0 / rho) + (b[:, None] + b[None, :]) / g + np.outer(b, b) * tot / g**2) - 2.0 * np.asarray(a)
+    return H
+
+
+def maxwell_single(a: float, b: float, kT: float, tol: float = 1e-15, maxit: int = 200):
+    """Coexisting (rho_gas, rho_liquid) of one component at kT < kT_cr.
+
+    Newton on mu(rho_g) = mu(rho_l), p(rho_g) = p(rho_l), started from the
+    spinodal-bracketed guesses; returns None above the critical temperature.
+    """
+    kTc, rc, _ = critical_point(a, b)
+    if kT >= kTc:
+        return None
+
+    def mu(r):
+        return kT * (np.log(r / (1 - b * r)) + 1 + b * r / (1 - b * r)) - 2 * a * r
+
+    def dmu(r):
+        return kT / (r * (1 - b * r) ** 2) - 2 * a
+
+    def p(r):
+        return r * kT / (1 - b * r) - a * r * r
+
+    def dp(r):
+        return kT / (1 - b * r) ** 2 - 2 * a * r
+
+    def bisect(fn, lo, hi):
+        flo = fn(lo)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            fm = fn(mid)
+            if (fm > 0) == (flo > 0):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        return 0.5 * (lo + hi)
+
+    # Start: the spinodals (dp/drho = 0) bracket the van der Waals loop; the
+    # guesses are the outer-branch densities at the mid-loop pressure.
+    sp_lo = bisect(dp, 1e-12, rc)
+    sp_hi = bisect(dp, rc, (1 - 1e-12) / b)
+    p_star = 0.5 * (max(p(sp_hi), 0.0) + p(sp_lo))
+    rg = bisect(lambda r: p(r) - p_star, 1e-300, sp_lo)
+    rl = bisect(lambda r: p(r) - p_star, sp_hi, (1 - 1e-15) / b)
+    for _ in range(maxit):
+        F = np.array([mu(rg) - mu(rl), p(rg) - p(rl)])
+        J = np.array([[dmu(rg), -dmu(rl)], [dp(rg), -dp(rl)]])
+        step = np.linalg.solve(J, F)
+        # damp to stay inside the physical domain
+        lam = 1.0
+        while True:
+            ng, nl = rg - lam * step[0], rl - lam * step[1]
+            if ng > 0 and nl * b < 1 and nl > ng:
+                break
+            lam *= 0.5
+        rg, rl = ng, nl
+        if np.max(np.abs(lam * step) / np.array([rg, rl])) < tol:
+            break
+    return rg, rl
+
+
+def coexistence_two_phase(rho_bar, rho_alpha, rho_beta, kT, a, b, tol=1e-14, maxit=100):
+    """Two coexisting bulk phases of overall composition rho_bar (common tangent).
+
+    Unknowns: the densities of phases alpha and beta and the volume fraction
+    phi of alpha.  Equations: equal mu^c, equal p (Sec. II), and the lever rule
+    phi rho_alpha + (1 - phi) rho_beta = rho_bar.  Solved by Newton with a
+    central-difference Jacobian, from the given starting phases.
+    """
+    rho_bar = np.asarray(rho_bar, dtype=float)
+    C = rho_bar.size
+    ra = np.asarray(rho_alpha, dtype=float)
+    rb = np.asarray(rho_beta, dtype=float)
+    d = ra - rb
+    phi0 = float(np.dot(rho_bar - rb, d) / np.dot(d, d))
+
+    def resid(z):
+        xa, xb, phi = z[:C], z[C:2 * C], z[2 * C]
+        return np.concatenate([chemical_potential(xa, kT, a, b) - chemical_potential(xb, kT, a, b),
+                               [pressure(xa, kT, a, b) - pressure(xb, kT, a, b)],
+                               phi * xa + (1.0 - phi) * xb - rho_bar])
+
+    z = np.concatenate([ra, rb, [phi0]])
+    n = z.size
+    for _ in range(maxit):
+        F = resid(z)
+        J = np.empty((n, n))
+        for k in range(n):
+            dz = np.zeros(n)
+            dz[k] = 1e-7 * max(1.0, abs(z[k]))
+            J[:, k] = (resid(z + dz) - resid(z - dz)) / (2 * dz[k])
+        step = np.linalg.solve(J, F)
+        lam = 1.0
+        while True:
+            t = z - lam * step
+            if np.all(t[:2 * C] > 0) and np.dot(b, t[:C]) < 1 and np.dot(b, t[C:2 * C]) < 1:
+                break
+            lam *= 0.5
+        z = t
+        if np.max(np.abs(lam * step)) < tol * max(1.0, np.max(np.abs(z))):
+            break
+    return z[:C], z[C:2 * C], float(z[2 * C])
+
+
+def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000):
+    """Quasi-brute-force three-phase free-energy minimisation (Appendix A).
+
+    Total volume 1 with particle numbers (NA, NB).  Phases 1 and 2 carry six
+    free variables (A1, B1, V1, A2, B2, V2); phase 3 follows from
+    conservation.  Each iteration evaluates the 6 x 3 array of trial moves
+    (each variable moved by +step, 0, -step), accepts the lowest total free
+    energy if it improves, otherwise halves the step; it stops once the step
+    no longer changes the free energy by more than the threshold.  The first
+    split follows the unstable eigenvector of the Hessian at (NA, NB).
+    Returns a list of (rho_A, rho_B, V) per phase with V > 0.
+    """
+    rho0 = np.array([NA, NB], dtype=float)
+    H = hessian(rho0, kT, a, b)
+    w, v = np.linalg.eigh(H)
+    d = v[:, 0]
+    eps = 0.05 * min(NA, NB)
+
+    def total(z):
+        A1, B1, V1, A2, B2, V2 = z
+        A3, B3, V3 = NA - A1 - A2, NB - B1 - B2, 1.0 - V1 - V2
+        F = 0.0
+        for A, B, V in ((A1, B1, V1), (A2, B2, V2), (A3, B3, V3)):
+            if V <= 0 or A <= 0 or B <= 0:
+                if V == 0 and A == 0 and B == 0:
+                    continue
+                return np.inf
+            r = np.array([A / V, B / V])
+            if np.dot(b, r) >= 1:
+                return np.inf
+            F += V * free_energy_density(r, kT, a, b)
+        return F
+
+    # phase 1 and 2 split along the unstable direction, phase 3 small
+    z = np.array([0.5 * NA + 0.5 * eps * d[0], 0.5 * NB + 0.5 * eps * d[1], 0.499,
+                  0.5 * NA - 0.5 * eps * d[0] - 1e-4 * NA, 0.5 * NB - 0.5 * eps * d[1] - 1e-4 * NB, 0.499])
+    F = total(z)
+    step = 0.01
+    it = 0
+    while it < max_iter:
+        it += 1
+        best, bestz = F, None
+        for k in range(6):
+            for sgn in (1.0, -1.0):
+                t = z.copy()
+                t[k] += sgn * step
+                Ft = total(t)
+                if Ft < best:
+                    best, bestz = Ft, t
+        if bestz is not None and F - best > 0:
+            z, F = bestz, best
+        else:
+            step *= 0.5
+            if step < threshold:
+                break
+    A1, B1, V1, A2, B2, V2 = z
+    phases = [(A1 / V1, B1 / V1, V1), (A2 / V2, B2 / V2, V2),
+              ((NA - A1 - A2) / (1 - V1 - V2), (NB - B1 - B2) / (1 - V1 - V2), 1 - V1 - V2)]
+    return phases, F
+
+
+def gamma_from_width_rule(kappa: float, rho_liquid: float, cs2: float = THETA_LB):
+    """gamma_mu from Eq. kappaGammaMuRelation: c_s^2 = 1 - 4 kappa rho_l gamma_mu."""
+    return (1.0 - cs2) / (4.0 * kappa * rho_liquid)
+
+
+def linear_growth_matrix(rho, kT, a, b, kappa, lap_symbol):
+    """H + K * (-lap_symbol): the quadratic form of the discrete free energy for a
+    Fourier mode whose discrete-Laplacian eigenvalue is lap_symbol (<= 0)."""
+    return hessian(rho, kT, a, b) - np.asarray(kappa) * lap_symbol

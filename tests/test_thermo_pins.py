@@ -1,0 +1,167 @@
+"""Pins of the oracle's bulk thermodynamics (oracle/thermo.py).
+
+Checked against closed forms of the paper (critical point, Eqs. tetcr, rhocr,
+pcr), the values printed in the figure captions of Sec. VI.A (tests/golden/
+vks_captions.csv), textbook identities (Maxwell equal-area rule, p = sum rho mu
+- f, mu = df/drho by finite differences) and the qualitative outcomes the
+paper reports for its baseline mixture (three phases at (0.8, 0.8)).
+"""
+import csv
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from oracle import thermo as T
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+A11, B1 = 9 / 49, 2 / 21
+
+
+def test_critical_point_closed_form():
+    """Eqs. tetcr/rhocr/pcr: at (kT_cr, rho_cr) the first and second density
+    derivatives of p vanish (an inflection of the isotherm), and p = p_cr."""
+    kTc, rc, pc = T.critical_point(A11, B1)
+    assert kTc == pytest.approx(4 / 7, rel=1e-15)
+    assert rc == pytest.approx(7 / 2, rel=1e-15)
+    assert pc == pytest.approx(3 / 4, rel=1e-15)
+    a, b = np.array([[A11]]), np.array([B1])
+    p = lambda r: T.pressure([r], kTc, a, b)
+    h = 1e-4
+    d1 = (p(rc + h) - p(rc - h)) / (2 * h)
+    d2 = (p(rc + h) - 2 * p(rc) + p(rc - h)) / h**2
+    assert abs(d1) < 1e-8 and abs(d2) < 1e-6
+    assert p(rc) == pytest.approx(pc, rel=1e-14)
+    # d^2 f / d rho^2 = (dp/drho)/rho vanishes there too: the Hessian is singular
+    assert abs(T.hessian([rc], kTc, a, b)[0, 0]) < 1e-14
+
+
+def test_chemical_potential_and_pressure_identities():
+    """mu^c = df/drho^c (finite differences) and p = sum_c rho^c mu^c - f (the
+    Euler relation of a homogeneous bulk, Sec. II)."""
+    rng = np.random.default_rng(0)
+    a = np.array([[0.2, 0.13, 0.1], [0.13, 0.25, 0.12], [0.1, 0.12, 0.18]])
+    b = np.array([0.1, 0.08, 0.12])
+    kT = 0.4
+    rho = rng.uniform(0.5, 2.0, 3)
+    mu = T.chemical_potential(rho, kT, a, b)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = 1e-6
+        fd = (T.free_energy_density(rho + e, kT, a, b) - T.free_energy_density(rho - e, kT, a, b)) / 2e-6
+        assert fd == pytest.approx(mu[c], rel=1e-8)
+    assert T.pressure(rho, kT, a, b) == pytest.approx(float(rho @ mu) - T.free_energy_density(rho, kT, a, b),
+                                                     rel=1e-13)
+    H = T.hessian(rho, kT, a, b)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = 1e-6
+        col = (T.chemical_potential(rho + e, kT, a, b) - T.chemical_potential(rho - e, kT, a, b)) / 2e-6
+        np.testing.assert_allclose(H[:, c], col, rtol=1e-7)
+
+
+@pytest.mark.parametrize("t", [0.6, 0.7, 0.8, 0.9, 0.97])
+def test_maxwell_equal_area(t):
+    """Maxwell construction: at coexistence the isotherm p(v), v = 1/rho,
+    encloses equal areas, i.e. integral of p dv from v_l to v_g equals
+    p_coex (v_g - v_l) (an independent route to the common tangent)."""
+    a, b = A11, B1
+    kT = t * 4 / 7
+    rg, rl = T.maxwell_single(a, b, kT)
+    pv = lambda v: kT / (v - b) - a / v**2
+    pco = T.pressure([rg], kT, np.array([[a]]), np.array([b]))
+    assert T.pressure([rl], kT, np.array([[a]]), np.array([b])) == pytest.approx(pco, rel=1e-12)
+    area, _ = quad(pv, 1 / rl, 1 / rg, epsabs=1e-14, epsrel=1e-13, limit=200)
+    assert area == pytest.approx(pco * (1 / rg - 1 / rl), rel=1e-10)
+    assert rg < 3.5 < rl
+
+
+def test_vks_parameters_from_captions():
+    """(xi, zeta, Lambda) printed in the captions of Sec. VI.A follow from the
+    printed critical parameters with a = 9 theta_cr / (8 rho_cr),
+    b = 1/(3 rho_cr) and a^{AB} = nu sqrt(a^A a^B) (Eq. vdwConstantAB); the
+    squared form a = 9 theta_cr^2 / (8 rho_cr) printed in Sec. VI.A does not
+    reproduce them.  Captions with a sign slip are compared in magnitude."""
+    rows = list(csv.DictReader(l for l in open(os.path.join(GOLDEN, "vks_captions.csv")) if not l.startswith("#")))
+    assert len(rows) == 11
+    squared_mismatch = 0
+    for r in rows:
+        ta, tb, rb, nu = (float(r[k]) for k in ("theta_cr_a", "theta_cr_b", "rho_cr_b", "nu"))
+        a, b = T.two_component_params(ta, tb, rb, nu)
+        got = dict(zip(("xi", "zeta", "Lambda"), T.vks_parameters(a, b)))
+        slips = r["sign_slip"].split()
+        for k in ("xi", "zeta", "Lambda"):
+            printed = float(r[k])
+            val = abs(got[k]) if k in slips else got[k]
+            ref = abs(printed) if k in slips else printed
+            assert abs(val - ref) <= 6e-7, (r["label"], k, got[k], printed)
+        # the squared reading
+        aA2, aB2 = 9 * ta**2 / 8, 9 * tb**2 / (8 * rb)
+        pa, pb = aA2 * 9, aB2 * 9 * rb**2
+        if abs((pb - pa) / (pa + pb) - got["zeta"]) > 1e-6:
+            squared_mismatch += 1
+    assert squared_mismatch >= 5
+
+
+def test_two_identical_components_coexist_at_maxwell():
+    """Two identical components with nu = 1 (Fig. graphTwoIdenticalComponents):
+    the common tangent joins phases of equal composition whose total
+    densities are the one-component Maxwell values (tie lines through the
+    origin)."""
+    a = np.full((2, 2), 0.45)
+    b = np.full(2, 1 / 3)
+    kT = 1 / 3
+    rg, rl = T.maxwell_single(0.45, 1 / 3, kT)
+    # paper units (theta_cr = 0.4, rho_cr = 1 at theta = 1/3)
+    assert rg == pytest.approx(0.2906987534627, rel=1e-12)
+    assert rl == pytest.approx(1.8511539047468, rel=1e-12)
+    xbar = 0.3
+    tot = 1.0
+    ra, rb, phi = T.coexistence_two_phase([xbar * tot, (1 - xbar) * tot], [0.3 * 1.8, 0.7 * 1.8],
+                                          [0.3 * 0.3, 0.7 * 0.3], kT, a, b)
+    assert ra.sum() == pytest.approx(rl, rel=1e-10)
+    assert rb.sum() == pytest.approx(rg, rel=1e-10)
+    assert ra[0] / ra.sum() == pytest.approx(xbar, rel=1e-10)
+    assert 0 < phi < 1
+
+
+def test_two_phase_coexistence_lowers_free_energy():
+    """A demixing point of the baseline mixture (Fig. graphBaselineCase,
+    nu = 0.5): the Newton common tangent has equal mu and p, and the split
+    state has lower free energy than the homogeneous one (Hessian unstable)."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    kT = 1 / 3
+    rbar = np.array([1.2, 0.4])
+    assert np.linalg.eigvalsh(T.hessian(rbar, kT, a, b))[0] < 0
+    ra, rb, phi = T.coexistence_two_phase(rbar, [1.5, 0.25], [0.6, 0.8], kT, a, b)
+    np.testing.assert_allclose(T.chemical_potential(ra, kT, a, b), T.chemical_potential(rb, kT, a, b), atol=1e-12)
+    assert T.pressure(ra, kT, a, b) == pytest.approx(T.pressure(rb, kT, a, b), abs=1e-12)
+    fsplit = phi * T.free_energy_density(ra, kT, a, b) + (1 - phi) * T.free_energy_density(rb, kT, a, b)
+    assert fsplit < T.free_energy_density(rbar, kT, a, b)
+
+
+def test_appendix_a_minimizer_three_phases():
+    """Appendix A direct search at (rho_A, rho_B) = (0.8, 0.8) of the baseline
+    mixture finds three coexisting phases (an A-rich and a B-rich liquid and
+    a vapour, Fig. graphBaselineNa008Nb008) with equal chemical potentials and
+    pressures to the minimiser's accuracy (Sec. VI.A quotes 1e-6)."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    kT = 1 / 3
+    phases, F = T.minimize_three_phase(0.8, 0.8, kT, a, b)
+    dens = [np.array([pa, pb]) for pa, pb, V in phases if V > 1e-3]
+    assert len(dens) == 3
+    mus = np.array([T.chemical_potential(d, kT, a, b) for d in dens])
+    ps = np.array([T.pressure(d, kT, a, b) for d in dens])
+    assert np.ptp(mus, axis=0).max() < 1e-4
+    assert np.ptp(ps) < 1e-5
+    comps = sorted(dens, key=lambda d: d[0] - d[1])
+    assert comps[0][1] > comps[0][0]  # B-rich
+    assert comps[2][0] > comps[2][1]  # A-rich
+    assert F < T.free_energy_density([0.8, 0.8], kT, a, b)
+
+
+def test_gamma_rule():
+    """Eq. kappaGammaMuRelation with c_s^2 = 1/3: 1/3 = 1 - 4 kappa rho_l gamma."""
+    g = T.gamma_from_width_rule(0.1, 6.7644704000989)
+    assert 1 - 4 * 0.1 * 6.7644704000989 * g == pytest.approx(1 / 3, rel=1e-15)
