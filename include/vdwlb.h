@@ -1,0 +1,174 @@
+/*
+ * vdwlb: MI355X (gfx950) library for the multicomponent van der Waals
+ * free-energy lattice Boltzmann method of Ridl & Wagner, "Lattice Boltzmann
+ * simulation of mixtures with multicomponent van der Waals equation of state"
+ * (arXiv:1805.07251).
+ *
+ * One time step (Eq. LBequation) of every component c on a periodic D2Q9
+ * lattice: pull-stream the populations f_i^c, take the moments rho^c and
+ * rho^c u^c (Sec. III), evaluate the chemical potential mu^c of the lattice
+ * van der Waals mixture free energy (Eq. discreteChemicalPotential), the
+ * mean-field force from its gradient (Eqs. forceMuLog / forceMuId), the
+ * inter-component friction with implicit true velocities (Eq. forceFriction),
+ * and the forced BGK collision (Eqs. BGKcollisionOperator, feq, with the
+ * second-moment correction of Eq. forceCorrectionsPsi).
+ *
+ * Conventions fixed by this interface
+ *  - Populations are stored structure-of-arrays: f[c][i][s] with plane stride
+ *    vdwlb_plane_elems() elements and site s = y*nx + x (x fastest).  The
+ *    velocity order is v_0 = (0,0), v_1..4 = (1,0),(0,1),(-1,0),(0,-1),
+ *    v_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
+ *  - A stored state is post-collision, pre-stream; a step reads f_i(x - v_i)
+ *    from one buffer and writes the new state to the other (ping-pong).
+ *  - Physical force convention: momentum of component c gains
+ *    G^c = -gamma_mu rho^c grad mu^c + theta grad rho^c + friction
+ *    (the printed forces are "minus the force", cf. Sec. IV); the lattice
+ *    temperature theta = 1/3 is fixed, kT is the thermodynamic temperature
+ *    entering mu and p only.
+ *  - Every device pointer is caller-owned memory on the device that was
+ *    current when the plan was created; the library never frees it.  Streams
+ *    are hipStream_t values passed as void* (NULL = the null stream).
+ *  - No exceptions cross this interface.  Kernel-side failures (rho^c <= 0,
+ *    eta = sum b^c rho^c >= 1, non-finite values) set a sticky device flag that
+ *    the next vdwlb_sync_status / vdwlb_moments call reports as
+ *    VDWLB_E_UNPHYSICAL and clears.  Calls on different plans are
+ *    independent; calls on one plan must not overlap.
+ */
+#ifndef VDWLB_H
+#define VDWLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VDWLB_ABI_VERSION 1
+#define VDWLB_MAX_COMPONENTS 4
+
+typedef int32_t vdwlb_status;
+enum {
+    VDWLB_OK = 0,
+    VDWLB_E_INVALID_ARG = 1, /* a NULL pointer, a bad size or a parameter outside its domain */
+    VDWLB_E_UNSUPPORTED = 2, /* a valid request this build does not implement (dim, C, dtype) */
+    VDWLB_E_DEVICE = 3,      /* a HIP runtime error; vdwlb_last_device_error() has its text */
+    VDWLB_E_UNPHYSICAL = 4   /* the sticky device flag: rho^c <= 0, eta >= 1 or a non-finite value */
+};
+
+enum { VDWLB_F64 = 0, VDWLB_F32 = 1 };             /* storage and arithmetic precision */
+enum { VDWLB_FORCE_LOG = 0, VDWLB_FORCE_NID = 1 }; /* Eq. forceMuLog / Eq. forceMuId */
+
+/* Description of one lattice and its parameters (Secs. II, III, V).
+ *   dim      2 (D2Q9).  1 (D1Q3) is reserved and returns VDWLB_E_UNSUPPORTED.
+ *   nx, ny   periodic extents, >= 1 each (small extents wrap several times).
+ *   ncomp    number of components C, 1 .. VDWLB_MAX_COMPONENTS.
+ *   dtype    VDWLB_F64 or VDWLB_F32.
+ *   force    VDWLB_FORCE_LOG (default of the paper's production runs) or NID.
+ *   kT       thermodynamic temperature in mu and p, > 0.
+ *   tau      BGK relaxation time, > 1/2.
+ *   gamma_mu prefactor of the chemical-potential force (Eq. forceMuNid), finite.
+ *   a        C*C row-major, symmetric: attraction a^{cc'} (Eq. a-psi).
+ *   b        C: excluded volume b^c, > 0.
+ *   kappa    C*C row-major, symmetric: gradient coefficients kappa^{cc'}
+ *            (Eq. kappa-psi); the 2-D interaction function is
+ *            psi(0) = 5/3 kappa - a, psi(v_i) = -3 w_i kappa.
+ *   lambda   C*C row-major, symmetric, diagonal ignored: friction
+ *            coefficients lambda^{cc'} (Eq. forceFriction); NULL means 1.
+ * The arrays are copied at plan creation. */
+typedef struct vdwlb_desc {
+    int32_t dim;
+    int32_t nx;
+    int32_t ny;
+    int32_t ncomp;
+    int32_t dtype;
+    int32_t force;
+    double kT;
+    double tau;
+    double gamma_mu;
+    const double* a;
+    const double* b;
+    const double* kappa;
+    const double* lambda;
+} vdwlb_desc;
+
+typedef struct vdwlb_plan vdwlb_plan;
+
+/* VDWLB_ABI_VERSION of the built library. */
+int32_t vdwlb_abi_version(void);
+
+/* Text for a status code (static storage). */
+const char* vdwlb_strerror(vdwlb_status s);
+
+/* Text of the last HIP error seen by this thread (static thread-local storage). */
+const char* vdwlb_last_device_error(void);
+
+/* Validate d and create a plan bound to the current device.  On success
+ * *out receives the plan; on failure *out is NULL. */
+vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out);
+
+/* Release the plan, its device flag word and its cached graphs (NULL is a no-op). */
+vdwlb_status vdwlb_plan_destroy(vdwlb_plan* plan);
+
+/* Elements between consecutive (c, i) planes of a population buffer
+ * (nx*ny rounded up to a multiple of 64). */
+int64_t vdwlb_plane_elems(const vdwlb_plan* plan);
+
+/* Bytes of one population buffer: 9 * C * plane_elems * sizeof(dtype).
+ * The caller allocates two (ping-pong).  0 for a NULL plan. */
+size_t vdwlb_state_bytes(const vdwlb_plan* plan);
+
+/* Initial state f_i^c = f^0_i(rho^c, u^c) (Eq. feq) with u^c = mom^c / rho^c.
+ *   f    device, vdwlb_state_bytes(plan) bytes, written.
+ *   rho  device, [C][ny][nx] in the plan dtype, read.
+ *   mom  device, [C][2][ny][nx] (x then y component) or NULL for u = 0.
+ * Asynchronous on stream. */
+vdwlb_status vdwlb_init(vdwlb_plan* plan, void* f, const void* rho, const void* mom, void* stream);
+
+/* Enqueue n >= 0 time steps alternating fA -> fB -> fA ...  On return
+ * *out_which (if not NULL) is 0 when the newest state is in fA and 1 when it
+ * is in fB (n odd).  fA and fB must be distinct state buffers.  Long runs are
+ * replayed from a captured hipGraph bound to (fA, fB); the graph is captured
+ * again when the pointers change.  Asynchronous on stream. */
+vdwlb_status vdwlb_step(vdwlb_plan* plan, void* fA, void* fB, int64_t n, void* stream, int32_t* out_which);
+
+/* Observables of the state f (the streamed populations, i.e. what the next
+ * step would see):
+ *   rho  [C][ny][nx]      rho^c = sum_i f_i^c(x - v_i)           (required)
+ *   mom  [C][2][ny][nx]   rho^c u^c = sum_i f_i^c(x - v_i) v_i    (or NULL)
+ *   mu   [C][ny][nx]      mu^c of Eq. discreteChemicalPotential, without the
+ *                         additive constant kT                    (or NULL)
+ *   p    [ny][nx]         bulk pressure sum_c [rho^c kT/(1-eta) -
+ *                         sum_c' a^{cc'} rho^c rho^c'] (Sec. II)   (or NULL)
+ * All device arrays in the plan dtype.  Synchronises stream and then returns
+ * what vdwlb_sync_status would. */
+vdwlb_status vdwlb_moments(vdwlb_plan* plan, const void* f, void* rho, void* mom, void* mu, void* p, void* stream);
+
+/* Synchronise stream, read and clear the sticky device flag of the plan. */
+vdwlb_status vdwlb_sync_status(vdwlb_plan* plan, void* stream);
+
+/* Number of tile schedules the sweep can use for this plan. */
+int32_t vdwlb_schedule_count(const vdwlb_plan* plan);
+
+/* Select schedule k (0 <= k < vdwlb_schedule_count) for later steps. */
+vdwlb_status vdwlb_set_schedule(vdwlb_plan* plan, int32_t k);
+
+/* Time every schedule on this plan's lattice (reads fA, overwrites fB), keep
+ * the fastest and report it in *chosen (may be NULL).  Synchronous. */
+vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* stream, int32_t* chosen);
+
+/* Liquid-gas coexistence of one van der Waals component (Eqs. tetcr, rhocr
+ * and the equal chemical potential / pressure conditions of Sec. II), used to
+ * initialise tanh slabs with bulk values as in Sec. V.  Host-only.  Returns
+ * VDWLB_E_INVALID_ARG when kT >= kT_cr or a, b, kT are not positive. */
+vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, double* rho_liquid);
+
+/* Device-to-device copy of nbytes with a plain streaming kernel; used as the
+ * bandwidth yardstick next to the sweep.  Asynchronous on stream. */
+vdwlb_status vdwlb_copy(void* dst, const void* src, size_t nbytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDWLB_H */

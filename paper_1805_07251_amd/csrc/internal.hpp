@@ -1,0 +1,51 @@
+// Host-side internals shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+struct vdwlb_plan {
+    int dim = 2, nx = 0, ny = 0, C = 0, dtype = 0, force = 0;
+    double kT = 0, tau = 1, gamma = 1;
+    std::vector<double> a, b, kappa, lam;  // row-major C x C (b: C)
+    int64_t plane = 0;
+    int device = 0;
+    int* d_flag = nullptr;  // sticky unphysical-state flag (device)
+    int sched = 0;          // index into the schedule table
+    // captured step sequence, bound to one (fA, fB) pair and schedule
+    hipGraphExec_t graph = nullptr;
+    const void* gA = nullptr;
+    const void* gB = nullptr;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace vdwlb {
+
+// Steps per graph replay = 2 * GRAPH_PAIRS (an even count, so every replay
+// returns the newest state to the first buffer).
+constexpr int GRAPH_PAIRS = 16;
+
+struct Schedule {
+    int tx, ty;
+    bool reload, nt;
+};
+
+int schedule_count();
+Schedule schedule_at(int k);
+int default_schedule(const vdwlb_plan& p);
+bool graphs_enabled();
+
+hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
+hipError_t launch_init(const vdwlb_plan& p, void* f, const void* rho, const void* mom, hipStream_t s);
+hipError_t launch_moments(const vdwlb_plan& p, const void* f, void* rho, void* mom, void* mu, void* pr,
+                          hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t nbytes, hipStream_t s);
+
+int32_t ensure_graph(vdwlb_plan& p, const void* fA, const void* fB);
+void release_graph(vdwlb_plan& p);
+
+bool maxwell_coexistence(double a, double b, double kT, double* rho_gas, double* rho_liquid);
+
+}  // namespace vdwlb

@@ -1,0 +1,99 @@
+// Host-side launch helpers shared by the per-precision dispatch units.
+#pragma once
+
+#include "internal.hpp"
+#include "sweep.hpp"
+
+namespace vdwlb {
+
+// Tile schedules of the sweep (TX x TY sites per workgroup, reload, NT
+// stores); the autotuner picks one per plan.
+#define VDWLB_SCHEDULES(X)          \
+    X(0, 64, 4, false, false)       \
+    X(1, 64, 8, false, false)       \
+    X(2, 32, 8, false, false)       \
+    X(3, 64, 16, false, false)      \
+    X(4, 128, 4, false, false)      \
+    X(5, 32, 16, false, false)      \
+    X(6, 64, 8, true, false)        \
+    X(7, 32, 16, true, false)       \
+    X(8, 64, 16, true, false)       \
+    X(9, 128, 4, true, false)       \
+    X(10, 64, 8, false, true)       \
+    X(11, 32, 16, false, true)      \
+    X(12, 64, 8, true, true)        \
+    X(13, 32, 16, true, true)
+
+#define VDWLB_SCHED_ENTRY(i, tx, ty, rl, nt) {tx, ty, rl, nt},
+constexpr Schedule SCHEDULES[] = {VDWLB_SCHEDULES(VDWLB_SCHED_ENTRY)};
+#undef VDWLB_SCHED_ENTRY
+constexpr int N_SCHEDULES = sizeof(SCHEDULES) / sizeof(SCHEDULES[0]);
+
+inline Geometry make_geometry(const vdwlb_plan& p, int tx, int ty) {
+    Geometry g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.plane = p.plane;
+    g.tiles_x = (p.nx + tx - 1) / tx;
+    // single-step wrapping needs every index to overshoot an extent by less
+    // than the extent itself: tile overhang plus a radius-3 reach
+    g.wrap_general = (p.nx < tx + 8 || p.ny < ty + 8) ? 1 : 0;
+    return g;
+}
+
+template <int C>
+Coeffs<C> make_coeffs(const vdwlb_plan& p) {
+    Coeffs<C> k;
+    k.kT = p.kT;
+    k.omega = 1.0 / p.tau;
+    k.cG = (p.tau - 0.25) / p.tau;
+    k.cL = 1.0 / (12.0 * p.tau);
+    k.gamma = p.gamma;
+    for (int c = 0; c < C; ++c) {
+        k.b[c] = p.b[c];
+        for (int d = 0; d < C; ++d) {
+            k.a2[c][d] = 2.0 * p.a[c * C + d];
+            k.kap[c][d] = p.kappa[c * C + d];
+            k.lam[c][d] = p.lam[c * C + d];
+        }
+    }
+    k.force = p.force;
+    return k;
+}
+
+template <typename T, int C, int TX, int TY, bool RL, bool NTS>
+hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    const Geometry g = make_geometry(p, TX, TY);
+    const Coeffs<C> k = make_coeffs<C>(p);
+    const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((k_sweep<T, C, TX, TY, RL, NTS>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin, (T*)fout, g, k,
+                       p.d_flag);
+    return hipGetLastError();
+}
+
+template <typename T, int C>
+hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    switch (p.sched) {
+#define VDWLB_SCHED_CASE(i, tx, ty, rl, nt) \
+    case i: return run_sweep<T, C, tx, ty, rl, nt>(p, fin, fout, s);
+        VDWLB_SCHEDULES(VDWLB_SCHED_CASE)
+#undef VDWLB_SCHED_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t run_sweep_typed(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    switch (p.C) {
+        case 1: return run_sweep_sched<T, 1>(p, fin, fout, s);
+        case 2: return run_sweep_sched<T, 2>(p, fin, fout, s);
+        case 3: return run_sweep_sched<T, 3>(p, fin, fout, s);
+        case 4: return run_sweep_sched<T, 4>(p, fin, fout, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_f64(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
+hipError_t launch_sweep_f32(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
+
+}  // namespace vdwlb

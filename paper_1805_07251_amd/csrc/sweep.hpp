@@ -1,0 +1,469 @@
+// Device code of the fused D2Q9 sweep of the multicomponent van der Waals
+// free-energy lattice Boltzmann method (Ridl & Wagner, arXiv:1805.07251).
+//
+// One kernel launch is one time step (Eq. LBequation) for every component:
+//   pull-stream -> moments (Sec. III) -> chemical potential
+//   (Eq. discreteChemicalPotential) -> mean-field force (Eq. forceMuLog or
+//   Eq. forceMuId) -> implicit friction (Eq. forceFriction) -> forced BGK
+//   collision (Eqs. BGKcollisionOperator, feq, forcing moments with
+//   Eq. forceCorrectionsPsi) -> store.
+//
+// Work decomposition: a workgroup owns a TX x TY tile of sites.  Phase 1 pulls
+// the 9C populations of each interior site into registers (they are reused by
+// the collision) and the densities of a radius-2 ring from neighbouring tiles
+// (re-read from L2/MALL, never stored), all into LDS.  Phase 2 evaluates the
+// chemical potential on the tile plus a radius-1 ring into LDS.  Phase 3
+// takes the isotropic gradients/Laplacian from LDS and collides.  HBM traffic
+// per site is one read and one write of the 9C populations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vdwlb {
+
+constexpr int Q = 9;
+constexpr int MAX_C = 4;
+
+// D2Q9 velocities, in the order fixed by the public header.
+constexpr int VX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int VY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+struct Geometry {
+    int nx, ny;
+    int64_t plane;     // elements between (c, i) planes
+    int tiles_x;       // tiles along x
+    int wrap_general;  // extents too small for single-step periodic wrapping
+};
+
+// Coefficients of one lattice, precomputed on the host in double.
+template <int C>
+struct Coeffs {
+    double kT;
+    double omega;  // 1/tau
+    double cG;     // (tau - 1/4)/tau: coefficient of G G / rho in S
+    double cL;     // 1/(12 tau): coefficient of Lap(rho) in S
+    double gamma;  // gamma_mu
+    double a2[C][C];
+    double kap[C][C];
+    double lam[C][C];
+    double b[C];
+    int force;  // 0 log, 1 nid
+};
+
+constexpr double THETA = 1.0 / 3.0;
+
+// The hardware hands consecutive workgroup ids to the 8 XCDs in turn.  Give
+// each XCD a contiguous range of tiles so that tiles that share halos run on
+// the same XCD (and L2) at about the same time.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int xcd = b & 7, k = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+__device__ __forceinline__ int wrapc(int v, int n, int general) {
+    if (general) {
+        int r = v % n;
+        return r < 0 ? r + n : r;
+    }
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// Offsets of the sources f_i(x - v_i) of site (x, y) inside one plane.
+__device__ __forceinline__ void pull_offsets(const Geometry& g, int x, int y, int (&o)[Q]) {
+    const int xm = wrapc(x - 1, g.nx, g.wrap_general), xp = wrapc(x + 1, g.nx, g.wrap_general);
+    const int ym = wrapc(y - 1, g.ny, g.wrap_general), yp = wrapc(y + 1, g.ny, g.wrap_general);
+    const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
+    o[0] = r0 + x;
+    o[1] = r0 + xm;
+    o[2] = rm + x;
+    o[3] = r0 + xp;
+    o[4] = rp + x;
+    o[5] = rm + xm;
+    o[6] = rm + xp;
+    o[7] = rp + xp;
+    o[8] = rp + xm;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void pull(const T* __restrict__ f, const Geometry& g, const int (&o)[Q], T (&p)[C][Q]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) p[c][i] = f[(int64_t)(c * Q + i) * g.plane + o[i]];
+}
+
+// rho = sum_i f_i, summed in velocity order.
+template <typename T>
+__device__ __forceinline__ T density(const T (&p)[Q]) {
+    T r = p[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) r += p[i];
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void momentum(const T (&p)[Q], T& jx, T& jy) {
+    jx = ((p[1] - p[3]) + (p[5] - p[6])) + (p[8] - p[7]);
+    jy = ((p[2] - p[4]) + (p[5] + p[6])) - (p[7] + p[8]);
+}
+
+// Isotropic 9-point stencils on an LDS array with row stride S, centred at
+// (ex, ey): gradient 3 sum_i w_i v_i g(x + v_i) and Laplacian
+// 6 sum_i w_i (g(x + v_i) - g(x)).
+template <typename T, int S>
+__device__ __forceinline__ T lap9(const T* a, int ex, int ey) {
+    const T* r0 = a + ey * S + ex;
+    const T axis = (r0[1] + r0[-1]) + (r0[S] + r0[-S]);
+    const T diag = (r0[S + 1] + r0[S - 1]) + (r0[-S - 1] + r0[-S + 1]);
+    return (T(4) * axis + diag - T(20) * r0[0]) * T(1.0 / 6.0);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void grad9(const T* a, int ex, int ey, T& gx, T& gy) {
+    const T* r0 = a + ey * S + ex;
+    const T ne = r0[S + 1], nw = r0[S - 1], sw = r0[-S - 1], se = r0[-S + 1];
+    gx = (T(4) * (r0[1] - r0[-1]) + ((ne - nw) + (se - sw))) * T(1.0 / 12.0);
+    gy = (T(4) * (r0[S] - r0[-S]) + ((ne + nw) - (sw + se))) * T(1.0 / 12.0);
+}
+
+__device__ __forceinline__ double dlog(double v) { return log(v); }
+__device__ __forceinline__ float dlog(float v) { return logf(v); }
+
+template <typename T>
+__device__ __forceinline__ bool finite_val(T v) {
+    return v == v && v - v == T(0);
+}
+
+// Chemical potential (Eq. discreteChemicalPotential without the constant kT,
+// with 2 sum psi rho(x + dx) = -2 a rho - kappa Lap(rho)) and the potential
+// phi whose gradient drives the force: gamma mu (log) or
+// gamma mu - theta ln rho (nid).  Returns false for unphysical input.
+template <typename T, int C>
+__device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], const Coeffs<C>& k, T (&phi)[C]) {
+    T eta = T(0), tot = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        eta += T(k.b[c]) * rho[c];
+        tot += rho[c];
+    }
+    const T free_vol = T(1) - eta;
+    const T inv = T(1) / free_vol;
+    const T lfree = dlog(free_vol);
+    bool ok = free_vol > T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        ok = ok && rho[c] > T(0);
+        const T lr = dlog(rho[c]);
+        T mu = T(k.kT) * ((lr - lfree) + T(k.b[c]) * tot * inv);
+#pragma unroll
+        for (int d = 0; d < C; ++d) mu -= T(k.a2[c][d]) * rho[d] + T(k.kap[c][d]) * lap[d];
+        phi[c] = T(k.gamma) * mu;
+        if (k.force == 1) phi[c] -= T(THETA) * lr;
+        ok = ok && finite_val(phi[c]);
+    }
+    return ok;
+}
+
+// Implicit friction (Eq. forceFriction with true velocities
+// uh = u + G/(2 rho), G including the friction): solve
+// rho^c uh^c - 1/2 sum_c' W^{cc'} (uh^c' - uh^c) = j^c + G_mu^c / 2,
+// W^{cc'} = lambda^{cc'} rho^c rho^c'/(rho^c + rho^c'), then
+// G_f^c = sum_c' W^{cc'} (uh^c' - uh^c), added to g in place.
+template <typename T, int C>
+__device__ __forceinline__ void friction(const T (&rho)[C], const T (&j)[C], T (&g)[C], const T (&W)[C][C]) {
+    if constexpr (C == 2) {
+        // closed form: the velocity difference shrinks by 1 + lambda/2
+        const T d0 = (j[1] + T(0.5) * g[1]) / rho[1] - (j[0] + T(0.5) * g[0]) / rho[0];
+        const T lam = W[0][1] * (rho[0] + rho[1]) / (rho[0] * rho[1]);
+        const T gf = W[0][1] * d0 / (T(1) + T(0.5) * lam);
+        g[0] += gf;
+        g[1] -= gf;
+    } else if constexpr (C > 2) {
+        T A[C][C], r[C], uh[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T diag = rho[c];
+#pragma unroll
+            for (int d = 0; d < C; ++d)
+                if (d != c) {
+                    diag += T(0.5) * W[c][d];
+                    A[c][d] = -T(0.5) * W[c][d];
+                }
+            A[c][c] = diag;
+            r[c] = j[c] + T(0.5) * g[c];
+        }
+#pragma unroll
+        for (int p = 0; p < C; ++p) {
+            const T ip = T(1) / A[p][p];
+#pragma unroll
+            for (int q = p + 1; q < C; ++q) {
+                const T f = A[q][p] * ip;
+#pragma unroll
+                for (int m = p; m < C; ++m) A[q][m] -= f * A[p][m];
+                r[q] -= f * r[p];
+            }
+        }
+#pragma unroll
+        for (int p = C - 1; p >= 0; --p) {
+            T acc = r[p];
+#pragma unroll
+            for (int m = p + 1; m < C; ++m) acc -= A[p][m] * uh[m];
+            uh[p] = acc / A[p][p];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T gf = T(0);
+#pragma unroll
+            for (int d = 0; d < C; ++d)
+                if (d != c) gf += W[c][d] * (uh[d] - uh[c]);
+            g[c] += gf;
+        }
+    }
+}
+
+// Forced BGK collision of one component at one site: returns the 9
+// post-collision populations in p (in place).
+template <typename T>
+__device__ __forceinline__ void collide(T (&p)[Q], T rho, T jx, T jy, T gx, T gy, T lap, T omega, T cG, T cL) {
+    const T ri = T(1) / rho;
+    const T ux = jx * ri, uy = jy * ri;
+    const T sxx = T(2) * gx * ux + cG * gx * gx * ri + cL * lap;
+    const T syy = T(2) * gy * uy + cG * gy * gy * ri + cL * lap;
+    const T sxy = gx * uy + gy * ux + cG * gx * gy * ri;
+    const T uu = ux * ux + uy * uy;
+    const T base = T(1) - T(1.5) * uu;
+    const T ftr = -T(1.5) * (sxx + syy);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        constexpr T W0 = T(4.0 / 9.0), W1 = T(1.0 / 9.0), W2 = T(1.0 / 36.0);
+        const T w = i == 0 ? W0 : (i < 5 ? W1 : W2);
+        const int vx = VX[i], vy = VY[i];
+        const T vu = T(vx) * ux + T(vy) * uy;
+        const T feq = w * rho * (base + vu * (T(3) + T(4.5) * vu));
+        const T svv = T(vx * vx) * sxx + T(vy * vy) * syy + T(2 * vx * vy) * sxy;
+        const T force = w * (T(3) * (T(vx) * gx + T(vy) * gy) + T(4.5) * svv + ftr);
+        p[i] = p[i] + omega * (feq - p[i]) + force;
+    }
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ void ring_coords(int r, int& ex, int& ey) {
+    constexpr int EX = TX + 4, EY = TY + 4;
+    if (r < 2 * EX) {
+        ey = r / EX;
+        ex = r - ey * EX;
+    } else if (r < 4 * EX) {
+        const int r2 = r - 2 * EX;
+        const int q = r2 / EX;
+        ey = EY - 2 + q;
+        ex = r2 - q * EX;
+    } else {
+        const int r3 = r - 4 * EX;
+        ey = 2 + (r3 >> 2);
+        const int k = r3 & 3;
+        ex = k < 2 ? k : EX - 4 + k;
+    }
+}
+
+// RELOAD: keep only rho and j of the interior site across the two barriers
+// and pull the populations of each component again right before its
+// collision (fewer live VGPRs, more waves per SIMD; the second read hits L2).  NTSTORE: non-temporal stores of the new
+// state, so that output lines do not displace halo lines in L2.
+template <typename T, int C, int TX, int TY, bool RELOAD, bool NTSTORE>
+__global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g,
+                                                    Coeffs<C> k, int* __restrict__ flag) {
+    constexpr int NT = TX * TY, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
+    constexpr int RING = EX * EY - TX * TY;
+    __shared__ T s_rho[C][EY * EX];
+    __shared__ T s_phi[C][MY * MX];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int ty_ = tile / g.tiles_x;
+    const int x0 = (tile - ty_ * g.tiles_x) * TX, y0 = ty_ * TY;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const int xs = wrapc(x, g.nx, g.wrap_general), ys = wrapc(y, g.ny, g.wrap_general);
+
+    // Phase 1: interior populations and densities.
+    T p[C][Q];
+    int o[Q];
+    pull_offsets(g, xs, ys, o);
+    pull<T, C>(fin, g, o, p);
+    T rho[C], jx[C], jy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = density<T>(p[c]);
+        momentum<T>(p[c], jx[c], jy[c]);
+        s_rho[c][(ly + 2) * EX + lx + 2] = rho[c];
+    }
+    // Densities of the radius-2 ring around the tile.
+    for (int r = threadIdx.x; r < RING; r += NT) {
+        int ex, ey;
+        ring_coords<TX, TY>(r, ex, ey);
+        const int hx = wrapc(x0 - 2 + ex, g.nx, g.wrap_general), hy = wrapc(y0 - 2 + ey, g.ny, g.wrap_general);
+        int oh[Q];
+        pull_offsets(g, hx, hy, oh);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T q[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) q[i] = fin[(int64_t)(c * Q + i) * g.plane + oh[i]];
+            s_rho[c][ey * EX + ex] = density<T>(q);
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: potential on the tile plus a radius-1 ring.
+    bool bad = false;
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        T r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
+            l[c] = lap9<T, EX>(s_rho[c], mx + 1, my + 1);
+        }
+        bad |= !potential<T, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+
+    // Phase 3: force, friction, collision, store.
+    if (x >= g.nx || y >= g.ny) return;
+    T gx[C], gy[C], lap[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T px, py, rx, ry;
+        grad9<T, MX>(s_phi[c], lx + 1, ly + 1, px, py);
+        grad9<T, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
+        lap[c] = lap9<T, EX>(s_rho[c], lx + 2, ly + 2);
+        gx[c] = -rho[c] * px;
+        gy[c] = -rho[c] * py;
+        if (k.force == 0) {
+            gx[c] += T(THETA) * rx;
+            gy[c] += T(THETA) * ry;
+        }
+    }
+    if constexpr (C > 1) {
+        T W[C][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = 0; d < C; ++d)
+                W[c][d] = c == d ? T(0) : T(k.lam[c][d]) * rho[c] * rho[d] / (rho[c] + rho[d]);
+        friction<T, C>(rho, jx, gx, W);
+        friction<T, C>(rho, jy, gy, W);
+    }
+    const int s = y * g.nx + x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if constexpr (RELOAD) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) p[c][i] = fin[(int64_t)(c * Q + i) * g.plane + o[i]];
+        }
+        collide<T>(p[c], rho[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T* dst = fout + (int64_t)(c * Q + i) * g.plane + s;
+            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], dst);
+            else *dst = p[c][i];
+        }
+    }
+}
+
+// f_i^c = f^0_i(rho^c, u^c) (Eq. feq).
+template <typename T, int C>
+__global__ void k_init(T* __restrict__ f, const T* __restrict__ rho, const T* __restrict__ mom, Geometry g) {
+    const int n = g.nx * g.ny;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const T r = rho[(int64_t)c * n + s];
+        T p[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) p[i] = T(0);
+        T jx = T(0), jy = T(0);
+        if (mom) {
+            jx = mom[(int64_t)(2 * c) * n + s];
+            jy = mom[(int64_t)(2 * c + 1) * n + s];
+        }
+        // collide with omega = 1 and no force from p = 0 gives exactly f^0
+        collide<T>(p, r, jx, jy, T(0), T(0), T(0), T(1), T(0), T(0));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[(int64_t)(c * Q + i) * g.plane + s] = p[i];
+    }
+}
+
+// rho^c and rho^c u^c of the streamed populations.
+template <typename T, int C>
+__global__ void k_moments(const T* __restrict__ f, T* __restrict__ rho, T* __restrict__ mom, Geometry g) {
+    const int n = g.nx * g.ny;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / g.nx, x = s - y * g.nx;
+    int o[Q];
+    Geometry gg = g;
+    gg.wrap_general = 1;
+    pull_offsets(gg, x, y, o);
+    T p[C][Q];
+    pull<T, C>(f, g, o, p);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[(int64_t)c * n + s] = density<T>(p[c]);
+        if (mom) {
+            T jx, jy;
+            momentum<T>(p[c], jx, jy);
+            mom[(int64_t)(2 * c) * n + s] = jx;
+            mom[(int64_t)(2 * c + 1) * n + s] = jy;
+        }
+    }
+}
+
+// mu^c (Eq. discreteChemicalPotential without the constant kT) and the bulk
+// pressure of Sec. II from a density field.
+template <typename T, int C>
+__global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restrict__ pr, Geometry g, Coeffs<C> k,
+                       int* __restrict__ flag) {
+    const int n = g.nx * g.ny;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / g.nx, x = s - y * g.nx;
+    const int xm = wrapc(x - 1, g.nx, 1), xp = wrapc(x + 1, g.nx, 1);
+    const int ym = wrapc(y - 1, g.ny, 1), yp = wrapc(y + 1, g.ny, 1);
+    T r[C], l[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const T* R = rho + (int64_t)c * n;
+        r[c] = R[s];
+        const T axis = (R[y * g.nx + xp] + R[y * g.nx + xm]) + (R[yp * g.nx + x] + R[ym * g.nx + x]);
+        const T diag = (R[yp * g.nx + xp] + R[yp * g.nx + xm]) + (R[ym * g.nx + xm] + R[ym * g.nx + xp]);
+        l[c] = (T(4) * axis + diag - T(20) * r[c]) * T(1.0 / 6.0);
+    }
+    Coeffs<C> kk = k;
+    kk.gamma = 1.0;
+    kk.force = 0;
+    T m[C];
+    const bool ok = potential<T, C>(r, l, kk, m);
+    if (!ok) atomicOr(flag, 1);
+    if (mu)
+#pragma unroll
+        for (int c = 0; c < C; ++c) mu[(int64_t)c * n + s] = m[c];
+    if (pr) {
+        T eta = T(0), tot = T(0), att = T(0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            eta += T(k.b[c]) * r[c];
+            tot += r[c];
+#pragma unroll
+            for (int d = 0; d < C; ++d) att += T(0.5) * T(k.a2[c][d]) * r[c] * r[d];
+        }
+        pr[s] = tot * T(k.kT) / (T(1) - eta) - att;
+    }
+}
+
+}  // namespace vdwlb

@@ -1,0 +1,94 @@
+"""The C-ABI library loads and exports every entry point include/vdwlb.h
+declares; host-only calls work without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+from paper_1805_07251_amd import vdwlb as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(vdwlb_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = V.lib()
+    decl = declared_symbols()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) <= set(V.symbols()) | {n for n in decl if hasattr(L, n)}
+
+
+def test_abi_version_and_strerror():
+    assert V.lib().vdwlb_abi_version() == 1
+    for s in range(5):
+        assert V.lib().vdwlb_strerror(s)
+
+
+@pytest.mark.parametrize("t", [0.6, 0.75, 0.8, 0.9, 0.99])
+def test_maxwell_helper_matches_oracle_thermo(t):
+    a, b = 9 / 49, 2 / 21
+    g, l = V.maxwell(a, b, t * 4 / 7)
+    rg, rl = T.maxwell_single(a, b, t * 4 / 7)
+    assert g == pytest.approx(rg, rel=1e-11)
+    assert l == pytest.approx(rl, rel=1e-11)
+
+
+def test_maxwell_helper_rejects_supercritical():
+    with pytest.raises(V.VdwlbError) as ei:
+        V.maxwell(9 / 49, 2 / 21, 4 / 7)
+    assert ei.value.status == V.E_INVALID_ARG
+
+
+def _desc(**kw):
+    import ctypes
+
+    a = np.array([[0.2, 0.1], [0.1, 0.2]])
+    b = np.array([0.1, 0.1])
+    k = np.array([[0.1, 0.05], [0.05, 0.1]])
+    p = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    args = dict(dim=2, nx=8, ny=8, ncomp=2, dtype=V.F64, force=V.FORCE_LOG, kT=0.4, tau=1.0, gamma_mu=0.25)
+    args.update(kw)
+    d = V.Desc(args["dim"], args["nx"], args["ny"], args["ncomp"], args["dtype"], args["force"], args["kT"],
+               args["tau"], args["gamma_mu"], p(a), p(b), p(k), None)
+    return d, (a, b, k)
+
+
+@pytest.mark.parametrize("bad", [dict(tau=0.5), dict(nx=0), dict(ncomp=0), dict(kT=-1.0), dict(dtype=7),
+                                 dict(force=3), dict(dim=3), dict(kT=float("nan"))])
+def test_plan_create_validates_before_touching_the_device(bad):
+    import ctypes
+
+    d, keep = _desc(**bad)
+    h = ctypes.c_void_p(1)
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
+    assert h.value is None
+
+
+def test_null_arguments():
+    import ctypes
+
+    assert V.lib().vdwlb_plan_create(None, None) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_step(None, None, None, 1, None, None) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_state_bytes(None) == 0
+    assert V.lib().vdwlb_plan_destroy(None) == V.OK
+
+
+def test_unsupported_dimension():
+    import ctypes
+
+    d, keep = _desc(dim=1)
+    h = ctypes.c_void_p()
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_UNSUPPORTED

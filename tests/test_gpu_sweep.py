@@ -1,0 +1,268 @@
+"""GPU parity of the fused D2Q9 sweep against the CPU oracle, through the C-ABI.
+
+Tolerances (max-norm of the density error relative to the largest density):
+  FP64: 1e-12 after 1000 steps of the 64x64 spinodal workload (its dynamics
+        are near-neutral, so per-step round-off of ~1e-16 grows only
+        linearly); 1e-13 after a few steps elsewhere.
+  FP32: 1e-4 after 1000 steps of the same workload.  Each step rounds the 9
+        stored populations of a site (unit round-off u = 2^-24) and their
+        sum, so the density carries a fresh error of about (Q + 1) u per step;
+        with near-neutral dynamics these add up like a random walk,
+        sqrt(1000) * 10 * u ~ 2e-5, and the bound allows five times that.
+Bitwise properties (uniform state, translation, schedule independence, graph
+replay) follow from every site running the same instruction sequence.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1805_07251_amd import inputs as I
+
+from ._util import oracle_params, oracle_run, rel_err, window_rho
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import lattice
+
+    return lattice
+
+
+def gpu_run(gpu, w, nsteps, dtype=None, sched=None, chunks=None):
+    lat = gpu.Lattice.from_workload(w, dtype=dtype)
+    if sched is not None:
+        lat.set_schedule(sched)
+    lat.init(w.rho)
+    for n in chunks or [nsteps]:
+        lat.run(n)
+    return lat
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def test_spinodal_small_f64_1000_steps(gpu, orc):
+    w = I.spinodal_small(0)
+    ref, st = oracle_run(orc, w, 1000)
+    assert st == 0
+    rho_ref, mom_ref, mu_ref, p_ref, _ = ref.moments()
+    lat = gpu_run(gpu, w, 1000)
+    rho, mom, mu, p = lat.moments()
+    assert rel_err(np_(rho), rho_ref) <= 1e-12
+    assert np.abs(np_(mom) - mom_ref).max() <= 1e-12 * np.abs(rho_ref).max()
+    assert np.abs(np_(mu) - mu_ref).max() <= 1e-11 * np.abs(mu_ref).max()
+    assert np.abs(np_(p) - p_ref).max() <= 1e-11 * np.abs(p_ref).max()
+
+
+def test_spinodal_small_f32_1000_steps(gpu, orc):
+    w = I.spinodal_small(0)
+    ref, _ = oracle_run(orc, w, 1000)
+    rho_ref = ref.moments()[0]
+    lat = gpu_run(gpu, w, 1000, dtype="f32")
+    rho = lat.moments(want_mu=False, want_p=False)[0]
+    assert rel_err(np_(rho), rho_ref) <= 1e-4
+
+
+N_SCHED = 14
+
+
+@pytest.mark.parametrize("sched", range(N_SCHED))
+def test_populations_one_step_every_schedule(gpu, orc, sched):
+    """Full population state after 3 steps on a ragged lattice (tiles do not
+    divide the extents) for every tile schedule."""
+    w = I.spinodal_small(1, n=64)
+    w.nx, w.ny = 77, 45
+    w.rho = np.random.default_rng(3).uniform(2.5, 2.75, (2, 45, 77))
+    ref, _ = oracle_run(orc, w, 3)
+    lat = gpu_run(gpu, w, 3, sched=sched)
+    f = np_(lat.state_sites())
+    np.testing.assert_allclose(f, ref.f, rtol=0, atol=1e-14)
+
+
+def test_schedules_bitwise_identical(gpu):
+    w = I.spinodal_small(2, n=64)
+    w.nx, w.ny = 131, 70
+    w.rho = np.random.default_rng(4).uniform(2.5, 2.75, (2, 70, 131))
+    outs = []
+    assert gpu_run(gpu, w, 0).schedule_count() == N_SCHED
+    for s in range(N_SCHED):
+        lat = gpu_run(gpu, w, 20, sched=s)
+        outs.append(np_(lat.state_sites()))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (5, 1), (3, 7), (9, 4), (70, 3)])
+def test_tiny_and_thin_lattices(gpu, orc, nx, ny):
+    """Extents smaller than the stencil reach wrap several times."""
+    w = I.spinodal_small(0)
+    w.nx, w.ny = nx, ny
+    w.rho = np.random.default_rng(nx * 31 + ny).uniform(2.55, 2.7, (2, ny, nx))
+    ref, _ = oracle_run(orc, w, 12)
+    lat = gpu_run(gpu, w, 12)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("C", [1, 3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_component_counts(gpu, orc, C, dtype):
+    w = I.mixture4(5, n=48, dtype=dtype, C=C) if C > 1 else I.spinodal_small(0, n=48)
+    if C == 1:
+        w.a, w.b, w.kappa, w.lam = w.a[:1, :1], w.b[:1], w.kappa[:1, :1], w.lam[:1, :1]
+        w.rho = w.rho[:1] * 2
+    w.lam = np.random.default_rng(9).uniform(0.5, 2.0, (C, C))
+    w.lam = 0.5 * (w.lam + w.lam.T)
+    ref, st = oracle_run(orc, w, 50)
+    assert st == 0
+    lat = gpu_run(gpu, w, 50, dtype=dtype)
+    rho = np_(lat.moments(want_mu=False, want_p=False)[0])
+    tol = 1e-13 if dtype == "f64" else 2e-5
+    assert rel_err(rho, ref.moments()[0]) <= tol
+
+
+def test_nid_force_and_tau(gpu, orc):
+    w = I.spinodal_small(3, n=40)
+    w.force, w.tau = 1, 0.8
+    ref, _ = oracle_run(orc, w, 60)
+    lat = gpu_run(gpu, w, 60)
+    assert rel_err(np_(lat.moments()[0]), ref.moments()[0]) <= 1e-13
+
+
+def test_initial_velocity(gpu, orc):
+    w = I.spinodal_small(4, n=32)
+    mom = np.random.default_rng(5).uniform(-0.05, 0.05, (2, 2, 32, 32)) * w.rho[:, None]
+    ref = orc.Lattice(oracle_params(orc, w), 2, 32, 32)
+    ref.init(w.rho, mom)
+    ref.run(10)
+    lat = gpu.Lattice.from_workload(w)
+    lat.init(w.rho, mom)
+    lat.run(10)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-14)
+
+
+def test_uniform_state_bitwise(gpu):
+    w = I.spinodal_small(0, n=96)
+    w.rho = np.ones_like(w.rho) * np.array([2.1, 3.0])[:, None, None]
+    lat = gpu_run(gpu, w, 40)
+    f = np_(lat.state_sites())
+    assert np.all(f == f[:, :, :1, :1])
+
+
+def test_translation_bitwise(gpu):
+    w = I.spinodal_small(6, n=64)
+    w.nx, w.ny = 100, 72
+    w.rho = np.random.default_rng(6).uniform(2.5, 2.75, (2, 72, 100))
+    a = np_(gpu_run(gpu, w, 15).state_sites())
+    w.rho = np.roll(w.rho, (13, -29), axis=(1, 2))
+    b = np_(gpu_run(gpu, w, 15).state_sites())
+    assert np.array_equal(b, np.roll(a, (13, -29), axis=(2, 3)))
+
+
+def test_mass_conservation(gpu):
+    w = I.spinodal_small(7, n=128)
+    lat = gpu_run(gpu, w, 0)
+    m0 = np_(lat.moments(False, False)[0]).sum(axis=(1, 2))
+    lat.run(500)
+    m1 = np_(lat.moments(False, False)[0]).sum(axis=(1, 2))
+    np.testing.assert_allclose(m1, m0, rtol=1e-12)
+
+
+def test_graph_replay_matches_eager(gpu):
+    """Long runs replay a captured graph; the result equals launching every
+    step eagerly, replay after replay."""
+    w = I.spinodal_small(8, n=64)
+    lat_g = gpu_run(gpu, w, 0)
+    os.environ["VDWLB_NO_GRAPH"] = "1"
+    try:
+        lat_e = gpu_run(gpu, w, 0)
+        for k in range(3):
+            lat_e.run(70)
+            ref = np_(lat_e.state_sites())
+            os.environ.pop("VDWLB_NO_GRAPH")
+            lat_g.run(70)
+            torch.cuda.synchronize()
+            assert np.array_equal(np_(lat_g.state_sites()), ref), k
+            os.environ["VDWLB_NO_GRAPH"] = "1"
+    finally:
+        os.environ.pop("VDWLB_NO_GRAPH", None)
+
+
+def test_unphysical_state_is_flagged(gpu):
+    from paper_1805_07251_amd import vdwlb as V
+
+    w = I.spinodal_small(0, n=32)
+    w.rho[0, 4:9, 5:10] = 12.0  # eta = b (rho1 + rho2) > 1 inside a block
+    lat = gpu_run(gpu, w, 0)
+    lat.run(1)
+    assert lat.status() == V.E_UNPHYSICAL
+    assert lat.status() == V.OK  # the flag is sticky until read
+    with pytest.raises(V.VdwlbError) as ei:
+        lat.run(1)
+        lat.moments()
+    assert ei.value.status == V.E_UNPHYSICAL
+
+
+def test_invalid_arguments(gpu):
+    from paper_1805_07251_amd import vdwlb as V
+
+    w = I.spinodal_small(0, n=16)
+    with pytest.raises(V.VdwlbError) as ei:
+        gpu.Lattice(16, 16, w.kT, w.a, w.b, w.kappa, tau=0.5)
+    assert ei.value.status == V.E_INVALID_ARG
+    bad = w.a.copy()
+    bad[0, 1] += 1e-3
+    with pytest.raises(V.VdwlbError):
+        gpu.Lattice(16, 16, w.kT, bad, w.b, w.kappa)
+    big = I.mixture4(0, n=8, C=5)
+    with pytest.raises(V.VdwlbError) as ei:
+        gpu.Lattice(8, 8, big.kT, big.a, big.b, big.kappa)
+    assert ei.value.status == V.E_UNSUPPORTED
+
+
+def test_autotune_keeps_results(gpu):
+    w = I.spinodal_small(9, n=256)
+    a = gpu_run(gpu, w, 0)
+    k = a.autotune()
+    assert 0 <= k < a.schedule_count()
+    a.init(w.rho)
+    a.run(10)
+    b = gpu_run(gpu, w, 10, sched=0)
+    assert np.array_equal(np_(a.state_sites()), np_(b.state_sites()))
+
+
+def test_spinodal_large_f64_sampled(gpu, orc):
+    """2048x2048 FP64, the benchmark's launch configuration: 10 steps, sampled
+    sites against the oracle on dependency windows, and mass conservation."""
+    w = I.spinodal_large(0)
+    lat = gpu.Lattice.from_workload(w)
+    lat.init(w.rho)
+    m0 = np_(lat.moments(False, False)[0]).sum(axis=(1, 2))
+    lat.autotune()
+    lat.init(w.rho)
+    lat.run(10)
+    rho = np_(lat.moments(False, False)[0])
+    rng = np.random.default_rng(11)
+    pts = [(0, 0), (w.nx - 1, w.ny - 1), (0, w.ny - 1), (w.nx - 1, 5)] + [
+        tuple(v) for v in rng.integers(0, 2048, (8, 2))]
+    for x, y in pts:
+        ref = window_rho(orc, w, x, y, 10)
+        assert np.abs(rho[:, y, x] - ref).max() <= 1e-13 * np.abs(ref).max(), (x, y)
+    np.testing.assert_allclose(rho.sum(axis=(1, 2)), m0, rtol=1e-12)
+
+
+def test_mixture4_f32_sampled(gpu, orc):
+    w = I.mixture4(0)
+    lat = gpu.Lattice.from_workload(w)
+    lat.init(w.rho)
+    lat.run(5)
+    rho = np_(lat.moments(False, False)[0])
+    for x, y in [(0, 0), (1023, 1023), (511, 3), (17, 900)]:
+        ref = window_rho(orc, w, x, y, 5)
+        assert np.abs(rho[:, y, x] - ref).max() <= 2e-6 * np.abs(ref).max(), (x, y)
