@@ -147,7 +147,10 @@ vdwlb_status vdwlb_moments(vdwlb_plan* plan, const void* f, void* rho, void* mom
 /* Synchronise stream, read and clear the sticky device flag of the plan. */
 vdwlb_status vdwlb_sync_status(vdwlb_plan* plan, void* stream);
 
-/* Number of tile schedules the sweep can use for this plan. */
+/* Number of schedules the sweep can use for this plan.  A schedule is a tile
+ * shape and kernel variant together with the order in which workgroups visit
+ * tiles (row-major ranges per XCD, or one vertical band of tile columns per
+ * XCD); every schedule computes bit-identical results. */
 int32_t vdwlb_schedule_count(const vdwlb_plan* plan);
 
 /* Select schedule k (0 <= k < vdwlb_schedule_count) for later steps. */
@@ -166,6 +169,102 @@ vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, doubl
 /* Device-to-device copy of nbytes with a plain streaming kernel; used as the
  * bandwidth yardstick next to the sweep.  Asynchronous on stream. */
 vdwlb_status vdwlb_copy(void* dst, const void* src, size_t nbytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched sweep: many independent lattices advanced by one persistent launch,
+ * the GPU form of the paper's phase-diagram runs (thousands of small flat-
+ * interface simulations with their own parameters, Sec. VI.A).
+ *
+ * Every instance has its own vdwlb_desc (size, kT, a, b, kappa, lambda, tau,
+ * gamma_mu, force); all share ncomp, dtype and the lattice height ny, which
+ * must be 1, 2, 4 or 8 (quasi-1-D lattices; other heights return
+ * VDWLB_E_UNSUPPORTED).  The states of all instances live in one pool buffer
+ * (two pools for ping-pong): instance k occupies the 9 * C * plane_k elements
+ * starting at vdwlb_batch_offset(k), laid out as a plain state.  Density
+ * arrays are packed the same way: instance k's [C][ny][nx] block starts at
+ * vdwlb_batch_density_offset(k).
+ * ------------------------------------------------------------------------ */
+typedef struct vdwlb_batch vdwlb_batch;
+
+/* Validate n descriptions (the rules of vdwlb_plan_create) and create a batch
+ * on the current device.  Instances are queued largest first. */
+vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch** out);
+
+/* Release the batch's instance table, queue, status words and graph. */
+vdwlb_status vdwlb_batch_destroy(vdwlb_batch* batch);
+
+/* Bytes of one pool (the caller allocates two). */
+size_t vdwlb_batch_state_bytes(const vdwlb_batch* batch);
+
+/* Element offset of instance k's state in a pool (-1 if k is out of range). */
+int64_t vdwlb_batch_offset(const vdwlb_batch* batch, int32_t k);
+
+/* Element offset of instance k's density block in packed density arrays. */
+int64_t vdwlb_batch_density_offset(const vdwlb_batch* batch, int32_t k);
+
+/* Launch shape of the persistent kernel: threads per workgroup (256 or 1024)
+ * and resident workgroups (0 = as many as the device holds, capped at n). */
+vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* batch, int32_t threads, int32_t blocks);
+
+/* pool = f^0(rho, u = 0) for every instance; rho is the packed density array
+ * (device, plan dtype).  Asynchronous on stream. */
+vdwlb_status vdwlb_batch_init(vdwlb_batch* batch, void* pool, const void* rho, void* stream);
+
+/* Packed densities rho^c = sum_i f_i^c(x - v_i) of every instance's state in
+ * pool.  Asynchronous on stream. */
+vdwlb_status vdwlb_batch_density(vdwlb_batch* batch, const void* pool, void* rho, void* stream);
+
+/* Advance every instance by nsteps (0 <= nsteps < 2^31) in one persistent
+ * launch (replayed from a hipGraph bound to poolA, poolB, nsteps and the launch
+ * shape).  *out_which as in vdwlb_step.  An instance that becomes unphysical
+ * stops at that step; its status word records the step and its state is left
+ * as it was then.  Asynchronous on stream. */
+vdwlb_status vdwlb_batch_run(vdwlb_batch* batch, void* poolA, void* poolB, int64_t nsteps, void* stream,
+                             int32_t* out_which);
+
+/* Synchronise stream and copy the per-instance status words of the last run
+ * into per_instance (host, n entries, may be NULL): 0 = completed, s > 0 =
+ * stopped unphysical at step s.  Returns VDWLB_E_UNPHYSICAL if any instance
+ * stopped. */
+vdwlb_status vdwlb_batch_status(vdwlb_batch* batch, int32_t* per_instance, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative) of the sweep, for gradients of a loss on
+ * the final densities with respect to the free-energy parameters of Sec. II
+ * (kT, a^{cc'}, b^c, kappa^{cc'}) through many steps.  FP64 plans with C = 1
+ * or 2 only (others return VDWLB_E_UNSUPPORTED).
+ *
+ * Parameter cotangent vector (double, device), vdwlb_adjoint_param_count()
+ * entries: kT, then a^{cd} for c <= d (row-major upper triangle), then b^c,
+ * then kappa^{cd} for c <= d.  An off-diagonal entry is the derivative with
+ * respect to the symmetric pair (a^{cd} = a^{dc} moved together).
+ * ------------------------------------------------------------------------ */
+
+/* Entries of the parameter cotangent vector (0 for a NULL plan). */
+int32_t vdwlb_adjoint_param_count(const vdwlb_plan* plan);
+
+/* Bytes of device workspace vdwlb_adjoint_segment needs for nsteps steps:
+ * three state buffers, the densities and momenta of every step of the
+ * segment (3 C nx ny doubles per step) and per-site intermediate fields. */
+size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* plan, int32_t nsteps);
+
+/* Cotangent of a state given cotangents of its read-out densities rho_bar
+ * ([C][ny][nx]) and momenta mom_bar ([C][2][ny][nx]); either may be NULL.
+ * fbar receives a full state (vdwlb_state_bytes).  This is the transpose of
+ * vdwlb_moments' density and momentum outputs.  Asynchronous on stream. */
+vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* plan, const void* rho_bar, const void* mom_bar, void* fbar,
+                                   void* stream);
+
+/* Reverse nsteps (>= 1) steps that start from the state f_ckpt:
+ * the forward steps are recomputed from f_ckpt (their densities and momenta
+ * kept in workspace), then fbar_io, the cotangent of the state after the
+ * segment, is replaced by the cotangent of f_ckpt, and the parameter
+ * cotangents of the segment are added to pbar_accum (device, see above).
+ * workspace: vdwlb_adjoint_workspace_bytes(plan, nsteps) bytes of device
+ * memory owned by the caller.  The summation order is fixed, so results are
+ * deterministic.  Asynchronous on stream. */
+vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
+                                   void* workspace, double* pbar_accum, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,126 @@
+"""Differentiation through many sweep steps: a torch.autograd.Function whose
+backward pass is the library's hand-written adjoint with segment
+checkpointing (the forward keeps the state every `ckpt` steps; the backward
+recomputes each segment from its checkpoint and reverses it).
+
+Parameters theta = [kT, a^{cd} (c <= d), b^c, kappa] with the gradient
+matrix kappa^{cd} = kappa * K_hat^{cd} (K_hat fixed), i.e. for two
+components theta = [kT, a11, a12, a22, b1, b2, kappa].  The output is the
+density field rho^c [C, ny, nx] of the final state.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import vdwlb as V
+from .lattice import Plan, _stream_ptr
+
+
+def theta_layout(C: int):
+    pairs = [(c, d) for c in range(C) for d in range(c, C)]
+    return pairs
+
+
+def theta_from_params(kT, a, b, kappa_scalar):
+    C = len(b)
+    pairs = theta_layout(C)
+    return np.array([kT] + [a[c][d] for c, d in pairs] + list(b) + [kappa_scalar], dtype=np.float64)
+
+
+def params_from_theta(theta, C, k_hat):
+    pairs = theta_layout(C)
+    kT = float(theta[0])
+    a = np.zeros((C, C))
+    for q, (c, d) in enumerate(pairs):
+        a[c, d] = a[d, c] = float(theta[1 + q])
+    b = np.array([float(v) for v in theta[1 + len(pairs):1 + len(pairs) + C]])
+    kappa = float(theta[-1]) * np.asarray(k_hat, dtype=np.float64)
+    return kT, a, b, kappa
+
+
+@dataclass
+class Spec:
+    """Everything but the differentiated parameters."""
+
+    nx: int
+    ny: int
+    C: int
+    k_hat: np.ndarray
+    nsteps: int
+    ckpt: int = 100
+    tau: float = 1.0
+    gamma_mu: float = 1.0
+    lam: np.ndarray | None = None
+    force: int = V.FORCE_LOG
+
+
+class VdwLBFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, rho0, spec: Spec):
+        th = theta.detach().cpu().numpy().astype(np.float64)
+        kT, a, b, kappa = params_from_theta(th, spec.C, spec.k_hat)
+        plan = Plan(spec.nx, spec.ny, kT, a, b, kappa, spec.tau, spec.gamma_mu, spec.lam, "f64", spec.force)
+        dev = rho0.device
+        n = plan.state_elems
+        bufs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+        r0 = rho0.detach().to(torch.float64).contiguous()
+        s = _stream_ptr()
+        V.check(V.lib().vdwlb_init(plan.handle, bufs[0].data_ptr(), r0.data_ptr(), None, s), "vdwlb_init")
+        ckpts, segs = [], []
+        cur, done = 0, 0
+        which = ctypes.c_int32()
+        while done < spec.nsteps:
+            m = min(spec.ckpt, spec.nsteps - done)
+            ckpts.append(bufs[cur].clone())
+            segs.append(m)
+            V.check(V.lib().vdwlb_step(plan.handle, bufs[cur].data_ptr(), bufs[1 - cur].data_ptr(), m, s,
+                                       ctypes.byref(which)), "vdwlb_step")
+            if which.value == 1:
+                cur = 1 - cur
+            done += m
+        C, ny, nx = spec.C, spec.ny, spec.nx
+        rho = torch.empty((C, ny, nx), dtype=torch.float64, device=dev)
+        mom = torch.empty((C, 2, ny, nx), dtype=torch.float64, device=dev)
+        V.check(V.lib().vdwlb_moments(plan.handle, bufs[cur].data_ptr(), rho.data_ptr(), mom.data_ptr(), None, None,
+                                      s), "vdwlb_moments")
+        ctx.plan, ctx.spec, ctx.ckpts, ctx.segs = plan, spec, ckpts, segs
+        ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        plan, spec = ctx.plan, ctx.spec
+        dev = grad_rho.device
+        s = _stream_ptr()
+        gb = grad_rho.detach().to(torch.float64).contiguous()
+        fbar = torch.empty(plan.state_elems, dtype=torch.float64, device=dev)
+        V.check(V.lib().vdwlb_moments_adjoint(plan.handle, gb.data_ptr(), None, fbar.data_ptr(), s),
+                "vdwlb_moments_adjoint")
+        npar = int(V.lib().vdwlb_adjoint_param_count(plan.handle))
+        pbar = torch.zeros(npar, dtype=torch.float64, device=dev)
+        ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(ctx.segs)))
+        ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
+        for ck, m in zip(reversed(ctx.ckpts), reversed(ctx.segs)):
+            V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(), ws.data_ptr(),
+                                                  pbar.data_ptr(), s), "vdwlb_adjoint_segment")
+        g = pbar.cpu().numpy()
+        C = spec.C
+        pairs = theta_layout(C)
+        na = len(pairs)
+        k_hat = np.asarray(spec.k_hat)
+        dkappa = sum(g[1 + na + C + q] * k_hat[c, d] for q, (c, d) in enumerate(pairs))
+        grad = np.concatenate([g[:1 + na + C], [dkappa]])
+        return torch.as_tensor(grad, dtype=ctx.theta_dtype, device=ctx.theta_device), None, None
+
+
+def run_and_grad(theta, rho0, spec: Spec, loss_fn):
+    """Loss of the final densities and its gradient with respect to theta."""
+    t = torch.as_tensor(theta, dtype=torch.float64).clone().requires_grad_(True)
+    rho = VdwLBFunction.apply(t, rho0, spec)
+    loss = loss_fn(rho)
+    loss.backward()
+    return float(loss.detach().cpu()), t.grad.detach().cpu().numpy()

@@ -1,0 +1,500 @@
+// Hand-written adjoint (reverse mode) of one sweep step, FP64, C = 1 or 2,
+// and the segment driver that recomputes the forward pass from a checkpoint.
+//
+// Forward step at site x (see the plain sweep): pulled populations p, moments
+// rho^c, j^c; L^c = Lap(rho^c); mu^c(rho, L) (Eq. discreteChemicalPotential);
+// phi^c = gamma mu^c (log) or gamma mu^c - theta ln rho^c (nid); mean-field
+// force G0^c = -rho^c grad phi^c [+ theta grad rho^c for log]; implicit
+// friction G = G0 + Gf (Eq. forceFriction); collision
+// f'_i = (1 - omega) p_i + omega feq_i(rho, j) + F_i(rho, j, G, L).
+//
+// Given the cotangent fb' of the new state, the adjoint runs three gathers:
+//  A (tile, LDS): recompute phi and G at the site from the stored moments;
+//     back-propagate through collision and friction: local density and
+//     momentum cotangents, the force cotangent G0b, the vectors
+//     Av = rho G0b (for the potential gradient) and Bv = G0b (for
+//     theta grad rho), and the Laplacian cotangent of the correction term.
+//  B: phib = div(Av) (transpose of the gradient stencil), mub = gamma phib,
+//     density cotangent through d mu / d rho, total Laplacian cotangent, and
+//     the parameter cotangents (kT, a, b, kappa), reduced per workgroup.
+//  C: rhob = local + B part + Lap(Lb) (the Laplacian is self-adjoint); the
+//     pulled-population cotangent pb_i = (1 - omega) fb'_i + rhob + jb.v_i
+//     is un-streamed: fb_i(x - v_i) = pb_i(x).
+#include <cstdio>
+#include <vector>
+
+#include "../../include/vdwlb.h"
+#include "launch.hpp"
+
+namespace vdwlb {
+namespace adj {
+
+constexpr int TX = 32, TY = 8;  // tile of kernel A
+constexpr int BLK = 256;        // workgroup of kernels B, C and the reduction
+
+// number of parameters in the cotangent vector:
+// kT, a^{cd} (c <= d), b^c, kappa^{cd} (c <= d)
+__host__ __device__ constexpr int n_params(int C) { return 1 + C * (C + 1) / 2 + C + C * (C + 1) / 2; }
+__host__ __device__ constexpr int pair_index(int C, int c, int d) {
+    // index of (min(c,d), max(c,d)) in the row-major upper triangle
+    return (c <= d) ? c * C - c * (c - 1) / 2 + (d - c) : d * C - d * (d - 1) / 2 + (c - d);
+}
+
+struct Fields {
+    const double* rho;  // [C][N] moments of the forward step
+    const double* mom;  // [C][2][N]
+    double* rhob_loc;   // [C][N]
+    double* jb;         // [C][2][N]
+    double* av;         // [C][2][N]
+    double* bv;         // [C][2][N]
+    double* lb;         // [C][N] Laplacian cotangent from the collision
+    double* rhob_b;     // [C][N]
+    double* lb_tot;     // [C][N]
+};
+
+__device__ __forceinline__ int wrapg(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Kernel A: collision, friction and force adjoint at each site.
+template <int C>
+__global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn, Geometry g, Coeffs<C> k,
+                                                  Fields F) {
+    constexpr int EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2, NT = TX * TY;
+    __shared__ double s_rho[C][EY * EX];
+    __shared__ double s_phi[C][MY * MX];
+    const int N = g.nx * g.ny;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
+    for (int e = threadIdx.x; e < EX * EY; e += NT) {
+        const int ey = e / EX, ex = e - ey * EX;
+        const int s = wrapg(y0 - 2 + ey, g.ny) * g.nx + wrapg(x0 - 2 + ex, g.nx);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_rho[c][e] = F.rho[(int64_t)c * N + s];
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        double r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
+            l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
+        }
+        potential<double, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = y * g.nx + x;
+    const double omega = k.omega, cG = k.cG, cL = k.cL;
+
+    double rho[C], jx[C], jy[C], g0x[C], g0y[C], dpx[C], dpy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = F.rho[(int64_t)c * N + s];
+        jx[c] = F.mom[(int64_t)(2 * c) * N + s];
+        jy[c] = F.mom[(int64_t)(2 * c + 1) * N + s];
+        double rx, ry;
+        grad9s<double, MX>(s_phi[c], lx + 1, ly + 1, dpx[c], dpy[c]);
+        grad9s<double, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
+        g0x[c] = -rho[c] * dpx[c];
+        g0y[c] = -rho[c] * dpy[c];
+        if (k.force == 0) {
+            g0x[c] += THETA * rx;
+            g0y[c] += THETA * ry;
+        }
+    }
+    // forward friction (C = 2 closed form)
+    double gx[C], gy[C];
+    double m = 0, K = 0, d0x = 0, d0y = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        gx[c] = g0x[c];
+        gy[c] = g0y[c];
+    }
+    if constexpr (C == 2) {
+        const double lam = k.lam[0][1];
+        m = rho[0] * rho[1] / (rho[0] + rho[1]);
+        K = lam / (1.0 + 0.5 * lam);
+        d0x = (jx[1] + 0.5 * g0x[1]) / rho[1] - (jx[0] + 0.5 * g0x[0]) / rho[0];
+        d0y = (jy[1] + 0.5 * g0y[1]) / rho[1] - (jy[0] + 0.5 * g0y[0]) / rho[0];
+        gx[0] += K * m * d0x;
+        gx[1] -= K * m * d0x;
+        gy[0] += K * m * d0y;
+        gy[1] -= K * m * d0y;
+    }
+
+    // collision adjoint: h = omega [rho M0 + 3 j.M + Q(j)/rho] + 3 G.M
+    //                        + [2 G.B.j + cG Q(G)]/rho + cL L tr B
+    double rb[C], jbx[C], jby[C], gbx[C], gby[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double M0 = 0, Mx = 0, My = 0, Mxx = 0, Myy = 0, Mxy = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+            const double fb = w * fbn[(int64_t)(c * Q + i) * g.plane + s];
+            const double vx = VX[i], vy = VY[i];
+            M0 += fb;
+            Mx += fb * vx;
+            My += fb * vy;
+            Mxx += fb * vx * vx;
+            Myy += fb * vy * vy;
+            Mxy += fb * vx * vy;
+        }
+        const double Bxx = 4.5 * Mxx - 1.5 * M0, Byy = 4.5 * Myy - 1.5 * M0, Bxy = 4.5 * Mxy;
+        const double r = rho[c], ri = 1.0 / r;
+        const double Jx = jx[c], Jy = jy[c], Gx = gx[c], Gy = gy[c];
+        const double Qj = Bxx * Jx * Jx + Byy * Jy * Jy + 2.0 * Bxy * Jx * Jy;
+        const double QG = Bxx * Gx * Gx + Byy * Gy * Gy + 2.0 * Bxy * Gx * Gy;
+        const double BJx = Bxx * Jx + Bxy * Jy, BJy = Bxy * Jx + Byy * Jy;
+        const double BGx = Bxx * Gx + Bxy * Gy, BGy = Bxy * Gx + Byy * Gy;
+        const double GBJ = Gx * BJx + Gy * BJy;
+        rb[c] = omega * (M0 - Qj * ri * ri) - (2.0 * GBJ + cG * QG) * ri * ri;
+        jbx[c] = omega * (3.0 * Mx + 2.0 * BJx * ri) + 2.0 * BGx * ri;
+        jby[c] = omega * (3.0 * My + 2.0 * BJy * ri) + 2.0 * BGy * ri;
+        gbx[c] = 3.0 * Mx + 2.0 * (BJx + cG * BGx) * ri;
+        gby[c] = 3.0 * My + 2.0 * (BJy + cG * BGy) * ri;
+        F.lb[(int64_t)c * N + s] = cL * (Bxx + Byy);
+    }
+    // friction adjoint: G = G0 + (+-) K m d0
+    double g0bx[C], g0by[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        g0bx[c] = gbx[c];
+        g0by[c] = gby[c];
+    }
+    if constexpr (C == 2) {
+        const double gfbx = gbx[0] - gbx[1], gfby = gby[0] - gby[1];
+        const double mb = K * (gfbx * d0x + gfby * d0y);
+        const double dbx = K * m * gfbx, dby = K * m * gfby;
+        const double s2 = (rho[0] + rho[1]) * (rho[0] + rho[1]);
+        rb[0] += mb * rho[1] * rho[1] / s2;
+        rb[1] += mb * rho[0] * rho[0] / s2;
+        // d0 = (j1 + G0_1/2)/rho1 - (j0 + G0_0/2)/rho0, per axis
+        const double i0 = 1.0 / rho[0], i1 = 1.0 / rho[1];
+        jbx[1] += dbx * i1;
+        jbx[0] -= dbx * i0;
+        jby[1] += dby * i1;
+        jby[0] -= dby * i0;
+        g0bx[1] += 0.5 * dbx * i1;
+        g0bx[0] -= 0.5 * dbx * i0;
+        g0by[1] += 0.5 * dby * i1;
+        g0by[0] -= 0.5 * dby * i0;
+        rb[1] -= (dbx * (jx[1] + 0.5 * g0x[1]) + dby * (jy[1] + 0.5 * g0y[1])) * i1 * i1;
+        rb[0] += (dbx * (jx[0] + 0.5 * g0x[0]) + dby * (jy[0] + 0.5 * g0y[0])) * i0 * i0;
+    }
+    // force adjoint, local part: G0 = -rho grad phi (+ theta grad rho)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rb[c] -= g0bx[c] * dpx[c] + g0by[c] * dpy[c];
+        F.rhob_loc[(int64_t)c * N + s] = rb[c];
+        F.jb[(int64_t)(2 * c) * N + s] = jbx[c];
+        F.jb[(int64_t)(2 * c + 1) * N + s] = jby[c];
+        F.av[(int64_t)(2 * c) * N + s] = rho[c] * g0bx[c];
+        F.av[(int64_t)(2 * c + 1) * N + s] = rho[c] * g0by[c];
+        F.bv[(int64_t)(2 * c) * N + s] = k.force == 0 ? g0bx[c] : 0.0;
+        F.bv[(int64_t)(2 * c + 1) * N + s] = k.force == 0 ? g0by[c] : 0.0;
+    }
+}
+
+// Discrete divergence with the gradient stencil: sum_i 3 w_i v_i . V(x + v_i)
+// (the transpose of the gradient up to a sign).
+__device__ __forceinline__ double div9(const double* vx, const double* vy, const Geometry& g, int x, int y) {
+    const int xm = wrapg(x - 1, g.nx), xp = wrapg(x + 1, g.nx), ym = wrapg(y - 1, g.ny), yp = wrapg(y + 1, g.ny);
+    const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
+    const double ax = 4.0 * (vx[r0 + xp] - vx[r0 + xm]) + ((vx[rp + xp] - vx[rp + xm]) + (vx[rm + xp] - vx[rm + xm]));
+    const double ay = 4.0 * (vy[rp + x] - vy[rm + x]) + ((vy[rp + xp] + vy[rp + xm]) - (vy[rm + xm] + vy[rm + xp]));
+    return (ax + ay) * (1.0 / 12.0);
+}
+
+__device__ __forceinline__ double lapg(const double* a, const Geometry& g, int x, int y) {
+    const int xm = wrapg(x - 1, g.nx), xp = wrapg(x + 1, g.nx), ym = wrapg(y - 1, g.ny), yp = wrapg(y + 1, g.ny);
+    const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
+    const double axis = (a[r0 + xp] + a[r0 + xm]) + (a[rp + x] + a[rm + x]);
+    const double diag = (a[rp + xp] + a[rp + xm]) + (a[rm + xm] + a[rm + xp]);
+    return (4.0 * axis + diag - 20.0 * a[r0 + x]) * (1.0 / 6.0);
+}
+
+// Kernel B: potential adjoint and parameter cotangents (one partial vector
+// per workgroup, reduced in a fixed order).
+template <int C>
+__global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F, double* __restrict__ partial) {
+    constexpr int NP = n_params(C);
+    __shared__ double s_red[NP][BLK];
+    const int N = g.nx * g.ny;
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    if (s < N) {
+        const int y = s / g.nx, x = s - y * g.nx;
+        double rho[C], L[C], mub[C], rb[C];
+        double eta = 0, tot = 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rho[c] = F.rho[(int64_t)c * N + s];
+            L[c] = lapg(F.rho + (int64_t)c * N, g, x, y);
+            eta += k.b[c] * rho[c];
+            tot += rho[c];
+        }
+        const double fv = 1.0 - eta, iv = 1.0 / fv;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double phib = div9(F.av + (int64_t)(2 * c) * N, F.av + (int64_t)(2 * c + 1) * N, g, x, y);
+            mub[c] = k.gamma * phib;
+            rb[c] = 0.0;
+            if (k.force == 0)
+                rb[c] -= THETA * div9(F.bv + (int64_t)(2 * c) * N, F.bv + (int64_t)(2 * c + 1) * N, g, x, y);
+            else
+                rb[c] -= THETA * phib / rho[c];
+        }
+        // d mu^c / d rho^d = kT [delta/rho^c + (b^c + b^d)/(1-eta) + b^c b^d tot/(1-eta)^2] - 2 a^{cd}
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = 0; d < C; ++d) {
+                double J = k.kT * ((k.b[c] + k.b[d]) * iv + k.b[c] * k.b[d] * tot * iv * iv) - k.a2[c][d];
+                if (c == d) J += k.kT / rho[c];
+                rb[d] += mub[c] * J;
+            }
+#pragma unroll
+        for (int d = 0; d < C; ++d) {
+            double lt = F.lb[(int64_t)d * N + s];
+#pragma unroll
+            for (int c = 0; c < C; ++c) lt -= mub[c] * k.kap[c][d];
+            F.lb_tot[(int64_t)d * N + s] = lt;
+            F.rhob_b[(int64_t)d * N + s] = rb[d];
+        }
+        // parameter cotangents of mu^c = kT [ln(rho^c/(1-eta)) + b^c tot/(1-eta)]
+        //                                 - sum_d (2 a^{cd} rho^d + kappa^{cd} L^d)
+        const int oa = 1, ob = 1 + C * (C + 1) / 2, ok = ob + C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc[0] += mub[c] * (log(rho[c] * iv) + k.b[c] * tot * iv);
+#pragma unroll
+            for (int d = 0; d < C; ++d) {
+                acc[oa + pair_index(C, c, d)] -= 2.0 * mub[c] * rho[d];
+                acc[ok + pair_index(C, c, d)] -= mub[c] * L[d];
+            }
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                double db = rho[e] * iv + k.b[c] * tot * rho[e] * iv * iv;
+                if (e == c) db += tot * iv;
+                acc[ob + e] += mub[c] * k.kT * db;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) s_red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = BLK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) s_red[q][threadIdx.x] += s_red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < NP) partial[(int64_t)blockIdx.x * NP + threadIdx.x] = s_red[threadIdx.x][0];
+}
+
+// Fixed-order reduction of the per-workgroup partials into pbar (+=).
+__global__ void k_adj_reduce(const double* __restrict__ partial, int nblocks, int np, double* __restrict__ pbar) {
+    __shared__ double s[BLK];
+    for (int q = 0; q < np; ++q) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += BLK) a += partial[(int64_t)b * np + q];
+        s[threadIdx.x] = a;
+        __syncthreads();
+        for (int h = BLK / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) pbar[q] += s[0];
+        __syncthreads();
+    }
+}
+
+// Kernel C: total density cotangent and the un-streamed population cotangent.
+template <int C>
+__global__ void __launch_bounds__(BLK) k_adj_c(const double* __restrict__ fbn, double* __restrict__ fbo, Geometry g,
+                                                double omega, Fields F) {
+    const int N = g.nx * g.ny;
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+    const int y = s / g.nx, x = s - y * g.nx;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double rb = F.rhob_loc[(int64_t)c * N + s] + F.rhob_b[(int64_t)c * N + s] +
+                          lapg(F.lb_tot + (int64_t)c * N, g, x, y);
+        const double jbx = F.jb[(int64_t)(2 * c) * N + s], jby = F.jb[(int64_t)(2 * c + 1) * N + s];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double pb = (1.0 - omega) * fbn[(int64_t)(c * Q + i) * g.plane + s] + rb + jbx * VX[i] +
+                              jby * VY[i];
+            const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
+            fbo[(int64_t)(c * Q + i) * g.plane + t] = pb;
+        }
+    }
+}
+
+// Cotangent of a state from the cotangent of its densities and momenta (the
+// transpose of the moments read-out): fb_i(x - v_i) = rhob(x) + jb(x).v_i.
+template <int C>
+__global__ void __launch_bounds__(BLK) k_moments_adj(const double* __restrict__ rhob, const double* __restrict__ momb,
+                                                      double* __restrict__ fb, Geometry g) {
+    const int N = g.nx * g.ny;
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= N) return;
+    const int y = s / g.nx, x = s - y * g.nx;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double rb = rhob ? rhob[(int64_t)c * N + s] : 0.0;
+        const double jbx = momb ? momb[(int64_t)(2 * c) * N + s] : 0.0;
+        const double jby = momb ? momb[(int64_t)(2 * c + 1) * N + s] : 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
+            fb[(int64_t)(c * Q + i) * g.plane + t] = rb + jbx * VX[i] + jby * VY[i];
+        }
+    }
+}
+
+}  // namespace adj
+}  // namespace vdwlb
+
+using namespace vdwlb;
+
+namespace {
+
+struct Layout {
+    int64_t N, plane, state;  // elements
+    int64_t f0, f1, fb, moms, fields, partial, total;
+    int nb_b, np;
+};
+
+Layout layout(const vdwlb_plan& p, int nsteps) {
+    Layout L;
+    L.N = (int64_t)p.nx * p.ny;
+    L.plane = p.plane;
+    L.state = (int64_t)Q * p.C * p.plane;
+    L.np = adj::n_params(p.C);
+    L.nb_b = (int)((L.N + adj::BLK - 1) / adj::BLK);
+    int64_t o = 0;
+    L.f0 = o;
+    o += L.state;
+    L.f1 = o;
+    o += L.state;
+    L.fb = o;
+    o += L.state;
+    L.moms = o;
+    o += (int64_t)nsteps * 3 * p.C * L.N;
+    L.fields = o;
+    o += 13 * (int64_t)p.C * L.N;
+    L.partial = o;
+    o += (int64_t)L.nb_b * L.np;
+    L.total = o;
+    return L;
+}
+
+adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
+    adj::Fields F;
+    const int C = p.C;
+    const double* mom0 = ws + L.moms + (int64_t)t * 3 * C * L.N;
+    F.rho = mom0;
+    F.mom = mom0 + (int64_t)C * L.N;
+    double* f = ws + L.fields;
+    F.rhob_loc = f;
+    F.jb = f + (int64_t)C * L.N;
+    F.av = f + 3 * (int64_t)C * L.N;
+    F.bv = f + 5 * (int64_t)C * L.N;
+    F.lb = f + 7 * (int64_t)C * L.N;
+    F.rhob_b = f + 8 * (int64_t)C * L.N;
+    F.lb_tot = f + 9 * (int64_t)C * L.N;
+    return F;
+}
+
+template <int C>
+hipError_t adjoint_step(const vdwlb_plan& p, const Layout& L, double* ws, int t, const double* fbn, double* fbo,
+                        double* pbar, hipStream_t s) {
+    Geometry g = make_geometry(p, adj::TX, adj::TY);
+    const Coeffs<C> k = make_coeffs<C>(p);
+    adj::Fields F = fields_at(p, L, ws, t);
+    const int tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
+    hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k, F);
+    hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, F, ws + L.partial);
+    hipLaunchKernelGGL(adj::k_adj_reduce, dim3(1), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial), L.nb_b,
+                       L.np, pbar);
+    hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega, F);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vdwlb_adjoint_param_count(const vdwlb_plan* p) { return p ? adj::n_params(p->C) : 0; }
+
+size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* p, int32_t nsteps) {
+    if (!p || nsteps < 1) return 0;
+    return (size_t)layout(*p, nsteps).total * sizeof(double);
+}
+
+vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const void* mom_bar, void* fbar,
+                                   void* stream) {
+    if (!p || !fbar || (!rho_bar && !mom_bar)) return VDWLB_E_INVALID_ARG;
+    if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
+    const Geometry g = make_geometry(*p, adj::TX, adj::TY);
+    const int nb = (int)(((int64_t)p->nx * p->ny + adj::BLK - 1) / adj::BLK);
+    hipError_t e = hipMemsetAsync(fbar, 0, vdwlb_state_bytes(p), (hipStream_t)stream);
+    if (e != hipSuccess) return set_device_error(e, "moments adjoint");
+    if (p->C == 1)
+        hipLaunchKernelGGL((adj::k_moments_adj<1>), dim3(nb), dim3(adj::BLK), 0, (hipStream_t)stream,
+                           (const double*)rho_bar, (const double*)mom_bar, (double*)fbar, g);
+    else
+        hipLaunchKernelGGL((adj::k_moments_adj<2>), dim3(nb), dim3(adj::BLK), 0, (hipStream_t)stream,
+                           (const double*)rho_bar, (const double*)mom_bar, (double*)fbar, g);
+    e = hipGetLastError();
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "moments adjoint");
+}
+
+vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io, void* workspace,
+                                   double* pbar_accum, void* stream) {
+    if (!p || !f_ckpt || !fbar_io || !workspace || !pbar_accum || nsteps < 1) return VDWLB_E_INVALID_ARG;
+    if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const Layout L = layout(*p, nsteps);
+    double* ws = (double*)workspace;
+    const size_t sb = (size_t)L.state * sizeof(double);
+    // forward recompute from the checkpoint, keeping the moments of each step
+    hipError_t e = hipMemcpyAsync(ws + L.f0, f_ckpt, sb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return set_device_error(e, "adjoint checkpoint copy");
+    for (int t = 0; t < nsteps; ++t) {
+        double* cur = ws + ((t & 1) ? L.f1 : L.f0);
+        double* nxt = ws + ((t & 1) ? L.f0 : L.f1);
+        double* m = ws + L.moms + (int64_t)t * 3 * p->C * L.N;
+        e = launch_moments(*p, cur, m, m + (int64_t)p->C * L.N, nullptr, nullptr, s);
+        if (e == hipSuccess) e = launch_sweep(*p, cur, nxt, s);
+        if (e != hipSuccess) return set_device_error(e, "adjoint forward recompute");
+    }
+    // reverse sweep: fbar_io <-> workspace buffer
+    double* bufs[2] = {(double*)fbar_io, ws + L.fb};
+    for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
+        const double* fbn = bufs[k & 1];
+        double* fbo = bufs[(k + 1) & 1];
+        e = p->C == 1 ? adjoint_step<1>(*p, L, ws, t, fbn, fbo, pbar_accum, s)
+                      : adjoint_step<2>(*p, L, ws, t, fbn, fbo, pbar_accum, s);
+        if (e != hipSuccess) return set_device_error(e, "adjoint step");
+    }
+    if (nsteps & 1) {
+        e = hipMemcpyAsync(fbar_io, ws + L.fb, sb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return set_device_error(e, "adjoint result copy");
+    }
+    return VDWLB_OK;
+}
+
+}  // extern "C"

@@ -35,26 +35,12 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
-extern "C" {
+namespace vdwlb {
 
-int32_t vdwlb_abi_version(void) { return VDWLB_ABI_VERSION; }
+int32_t set_device_error(hipError_t e, const char* where) { return dev_fail(e, where); }
 
-const char* vdwlb_strerror(vdwlb_status s) {
-    switch (s) {
-        case VDWLB_OK: return "ok";
-        case VDWLB_E_INVALID_ARG: return "invalid argument";
-        case VDWLB_E_UNSUPPORTED: return "unsupported configuration";
-        case VDWLB_E_DEVICE: return "HIP device error";
-        case VDWLB_E_UNPHYSICAL: return "unphysical state (rho <= 0, eta >= 1 or non-finite value)";
-        default: return "unknown status";
-    }
-}
-
-const char* vdwlb_last_device_error(void) { return g_last_error; }
-
-vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out) {
-    if (!out) return VDWLB_E_INVALID_ARG;
-    *out = nullptr;
+// Every rule of vdwlb_desc, checked on host data only.
+int32_t validate_desc(const vdwlb_desc* d) {
     if (!d) return VDWLB_E_INVALID_ARG;
     const int C = d->ncomp;
     if (d->nx < 1 || d->ny < 1 || C < 1) return VDWLB_E_INVALID_ARG;
@@ -79,28 +65,61 @@ vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out) {
     }
     if (d->dim != 2) return VDWLB_E_UNSUPPORTED;
     if (C > VDWLB_MAX_COMPONENTS) return VDWLB_E_UNSUPPORTED;
+    return VDWLB_OK;
+}
 
-    vdwlb_plan* p = new (std::nothrow) vdwlb_plan();
+// Host part of a plan (no device resources) from a validated description.
+vdwlb_plan plan_from_desc(const vdwlb_desc& d) {
+    vdwlb_plan p;
+    const int C = d.ncomp;
+    p.dim = d.dim;
+    p.nx = d.nx;
+    p.ny = d.ny;
+    p.C = C;
+    p.dtype = d.dtype;
+    p.force = d.force;
+    p.kT = d.kT;
+    p.tau = d.tau;
+    p.gamma = d.gamma_mu;
+    p.a.assign(d.a, d.a + C * C);
+    p.b.assign(d.b, d.b + C);
+    p.kappa.assign(d.kappa, d.kappa + C * C);
+    p.lam.assign(C * C, 1.0);
+    if (d.lambda)
+        for (int i = 0; i < C * C; ++i) p.lam[i] = d.lambda[i];
+    for (int c = 0; c < C; ++c) p.lam[c * C + c] = 0.0;
+    const int64_t n = (int64_t)d.nx * d.ny;
+    p.plane = (n + 63) / 64 * 64;
+    p.sched = default_schedule(p);
+    return p;
+}
+
+}  // namespace vdwlb
+
+extern "C" {
+
+int32_t vdwlb_abi_version(void) { return VDWLB_ABI_VERSION; }
+
+const char* vdwlb_strerror(vdwlb_status s) {
+    switch (s) {
+        case VDWLB_OK: return "ok";
+        case VDWLB_E_INVALID_ARG: return "invalid argument";
+        case VDWLB_E_UNSUPPORTED: return "unsupported configuration";
+        case VDWLB_E_DEVICE: return "HIP device error";
+        case VDWLB_E_UNPHYSICAL: return "unphysical state (rho <= 0, eta >= 1 or non-finite value)";
+        default: return "unknown status";
+    }
+}
+
+const char* vdwlb_last_device_error(void) { return g_last_error; }
+
+vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out) {
+    if (!out) return VDWLB_E_INVALID_ARG;
+    *out = nullptr;
+    const vdwlb_status st = validate_desc(d);
+    if (st != VDWLB_OK) return st;
+    vdwlb_plan* p = new (std::nothrow) vdwlb_plan(plan_from_desc(*d));
     if (!p) return VDWLB_E_DEVICE;
-    p->dim = d->dim;
-    p->nx = d->nx;
-    p->ny = d->ny;
-    p->C = C;
-    p->dtype = d->dtype;
-    p->force = d->force;
-    p->kT = d->kT;
-    p->tau = d->tau;
-    p->gamma = d->gamma_mu;
-    p->a.assign(d->a, d->a + C * C);
-    p->b.assign(d->b, d->b + C);
-    p->kappa.assign(d->kappa, d->kappa + C * C);
-    p->lam.assign(C * C, 1.0);
-    if (d->lambda)
-        for (int i = 0; i < C * C; ++i) p->lam[i] = d->lambda[i];
-    for (int c = 0; c < C; ++c) p->lam[c * C + c] = 0.0;
-    const int64_t n = (int64_t)d->nx * d->ny;
-    p->plane = (n + 63) / 64 * 64;
-    p->sched = default_schedule(*p);
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_flag, 256);
     if (e == hipSuccess) e = hipMemset(p->d_flag, 0, 256);
@@ -175,12 +194,14 @@ vdwlb_status vdwlb_moments(vdwlb_plan* p, const void* f, void* rho, void* mom, v
     return vdwlb_sync_status(p, stream);
 }
 
-int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? schedule_count() : 0; }
+int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? 2 * schedule_count() : 0; }
 
 vdwlb_status vdwlb_set_schedule(vdwlb_plan* p, int32_t k) {
-    if (!p || k < 0 || k >= schedule_count()) return VDWLB_E_INVALID_ARG;
-    if (k != p->sched) release_graph(*p);
-    p->sched = k;
+    if (!p || k < 0 || k >= 2 * schedule_count()) return VDWLB_E_INVALID_ARG;
+    const int sched = k % schedule_count(), mode = k / schedule_count();
+    if (sched != p->sched || mode != p->map_mode) release_graph(*p);
+    p->sched = sched;
+    p->map_mode = mode;
     return VDWLB_OK;
 }
 
@@ -193,9 +214,11 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     const int64_t sites = (int64_t)p->nx * p->ny;
     const int reps = sites >= (1 << 20) ? 10 : 50;
     float best = 1e30f;
-    int best_k = p->sched;
-    for (int k = 0; k < schedule_count(); ++k) {
+    int best_k = p->sched, best_m = p->map_mode;
+    for (int km = 0; km < 2 * schedule_count(); ++km) {
+        const int k = km >> 1;
         p->sched = k;
+        p->map_mode = km & 1;
         hipError_t e = hipSuccess;
         for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch_sweep(*p, fA, fB, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
@@ -212,13 +235,15 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
         if (ms < best) {
             best = ms;
             best_k = k;
+            best_m = p->map_mode;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_graph(*p);
     p->sched = best_k;
-    if (chosen) *chosen = best_k;
+    p->map_mode = best_m;
+    if (chosen) *chosen = best_k + best_m * schedule_count();
     return VDWLB_OK;
 }
 

@@ -1,0 +1,406 @@
+// Batched sweep: many independent quasi-1-D lattices (all of height NY, any
+// width, own parameters) advanced by one persistent launch.
+//
+// Workgroups take instances from a queue ordered largest first (longest
+// processing time first) and run every step of an instance before taking the
+// next one, so an instance's two population buffers stay in L2/MALL for its
+// whole run instead of streaming through HBM each step.  Each step walks the
+// instance in full-height strips of TX columns whose rows wrap inside LDS
+// (strip_step), with exactly the per-site arithmetic of the plain sweep.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/vdwlb.h"
+#include "launch.hpp"
+
+namespace vdwlb {
+
+template <int C>
+struct Instance {
+    Geometry g;
+    int64_t offset;      // element offset of the state in a pool
+    int64_t rho_offset;  // element offset of the [C][ny][nx] block in packed density arrays
+    Coeffs<C> k;
+};
+
+__global__ void k_reset_counter(int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <typename T, int C, int TX, int NY>
+__global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict__ inst, const int* __restrict__ order,
+                                                    int n, T* poolA, T* poolB, int nsteps, int* counter,
+                                                    int* __restrict__ status) {
+    using L = StripLds<TX, NY>;
+    __shared__ T s_rho[C * L::SR];
+    __shared__ T s_phi[C * L::SP];
+    __shared__ int s_job, s_bad;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_job = atomicAdd(counter, 1);
+            s_bad = 0;
+        }
+        __syncthreads();
+        // the job index is the same for the whole workgroup: keep it (and so
+        // the instance's coefficients) in scalar registers
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        if (job >= n) return;  // uniform: every wave exits, the queue is drained
+        const int id = __builtin_amdgcn_readfirstlane(order[job]);
+        const Instance<C>& I = inst[id];
+        Geometry g = I.g;
+        g.wrap_general = g.nx < TX + 8 ? 1 : 0;
+        T* A = poolA + I.offset;
+        T* B = poolB + I.offset;
+        int fail = 0;
+        for (int t = 0; t < nsteps; ++t) {
+            const T* src = (t & 1) ? B : A;
+            T* dst = (t & 1) ? A : B;
+            bool bad = false;
+            for (int x0 = 0; x0 < g.nx; x0 += TX) {
+                bad |= strip_step<T, C, TX, NY, false>(src, dst, g, I.k, x0, s_rho, s_phi);
+                __syncthreads();  // LDS reuse by the next strip; orders this step's stores before the next step
+            }
+            if (bad) s_bad = 1;
+            __syncthreads();
+            if (s_bad) {
+                fail = t + 1;
+                break;
+            }
+        }
+        if (threadIdx.x == 0) status[id] = fail;
+        __syncthreads();
+    }
+}
+
+// f = f^0(rho, u = 0) for every instance; one workgroup per instance.
+template <typename T, int C>
+__global__ void k_batch_init(const Instance<C>* __restrict__ inst, T* __restrict__ pool, const T* __restrict__ rho) {
+    const Instance<C>& I = inst[blockIdx.x];
+    const int n = I.g.nx * I.g.ny;
+    for (int s = threadIdx.x; s < n; s += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T p[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) p[i] = T(0);
+            collide<T>(p, rho[I.rho_offset + (int64_t)c * n + s], T(0), T(0), T(0), T(0), T(0), T(1), T(0), T(0));
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pool[I.offset + (int64_t)(c * Q + i) * I.g.plane + s] = p[i];
+        }
+}
+
+// Densities of the streamed populations of every instance.
+template <typename T, int C>
+__global__ void k_batch_rho(const Instance<C>* __restrict__ inst, const T* __restrict__ pool, T* __restrict__ rho) {
+    const Instance<C>& I = inst[blockIdx.x];
+    Geometry g = I.g;
+    g.wrap_general = 1;
+    const int n = g.nx * g.ny;
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        const int y = s / g.nx, x = s - y * g.nx;
+        pull_density<T, C>(pool + I.offset, g, x, y, rho + I.rho_offset + s, n);
+    }
+}
+
+}  // namespace vdwlb
+
+using namespace vdwlb;
+
+struct vdwlb_batch {
+    int n = 0, C = 0, dtype = 0, ny = 0;
+    std::vector<int64_t> offset, rho_offset, sites;
+    int64_t pool_elems = 0, rho_elems = 0;
+    void* d_inst = nullptr;  // Instance<C>[n]
+    int* d_order = nullptr;
+    int* d_status = nullptr;
+    int* d_counter = nullptr;
+    int threads = 256;  // workgroup size of the persistent kernel
+    int blocks = 0;     // resident workgroups (0: fill the device)
+    hipGraphExec_t graph = nullptr;
+    const void *gA = nullptr, *gB = nullptr;
+    int64_t gsteps = -1;
+    int gblocks = 0, gthreads = 0;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+vdwlb_status bfail(hipError_t e, const char* where) { return set_device_error(e, where); }
+
+template <typename T, int C, int TX, int NY>
+hipError_t launch_batch_shape(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<T, C, TX, NY>), dim3(blocks), dim3(TX * NY), 0, s, (const Instance<C>*)b.d_inst,
+                       b.d_order, b.n, (T*)A, (T*)B, nsteps, b.d_counter, b.d_status);
+    return hipGetLastError();
+}
+
+template <typename T, int C, int THREADS>
+hipError_t launch_batch_ny(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    switch (b.ny) {
+        case 1:
+            if constexpr (THREADS <= 256) return launch_batch_shape<T, C, THREADS, 1>(b, A, B, nsteps, blocks, s);
+            break;
+        case 2:
+            if constexpr (THREADS <= 256) return launch_batch_shape<T, C, THREADS / 2, 2>(b, A, B, nsteps, blocks, s);
+            break;
+        case 4: return launch_batch_shape<T, C, THREADS / 4, 4>(b, A, B, nsteps, blocks, s);
+        case 8: return launch_batch_shape<T, C, THREADS / 8, 8>(b, A, B, nsteps, blocks, s);
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int C>
+hipError_t launch_batch_c(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    // 1024-thread workgroups only for heights of 4 and 8 (wide strips of
+    // 1- and 2-row lattices would exceed the LDS of a workgroup)
+    if (b.threads == 1024 && b.ny >= 4) return launch_batch_ny<T, C, 1024>(b, A, B, nsteps, blocks, s);
+    return launch_batch_ny<T, C, 256>(b, A, B, nsteps, blocks, s);
+}
+
+template <typename T>
+hipError_t launch_batch_t(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    switch (b.C) {
+        case 1: return launch_batch_c<T, 1>(b, A, B, nsteps, blocks, s);
+        case 2: return launch_batch_c<T, 2>(b, A, B, nsteps, blocks, s);
+        case 3: return launch_batch_c<T, 3>(b, A, B, nsteps, blocks, s);
+        case 4: return launch_batch_c<T, 4>(b, A, B, nsteps, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return b.dtype == VDWLB_F64 ? launch_batch_t<double>(b, A, B, nsteps, blocks, s)
+                                : launch_batch_t<float>(b, A, B, nsteps, blocks, s);
+}
+
+template <typename T, int C>
+hipError_t aux_c(vdwlb_batch& b, int what, void* pool, void* rho, hipStream_t s) {
+    if (what == 0)
+        hipLaunchKernelGGL((k_batch_init<T, C>), dim3(b.n), dim3(256), 0, s, (const Instance<C>*)b.d_inst, (T*)pool,
+                           (const T*)rho);
+    else
+        hipLaunchKernelGGL((k_batch_rho<T, C>), dim3(b.n), dim3(256), 0, s, (const Instance<C>*)b.d_inst,
+                           (const T*)pool, (T*)rho);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t aux_t(vdwlb_batch& b, int what, void* pool, void* rho, hipStream_t s) {
+    switch (b.C) {
+        case 1: return aux_c<T, 1>(b, what, pool, rho, s);
+        case 2: return aux_c<T, 2>(b, what, pool, rho, s);
+        case 3: return aux_c<T, 3>(b, what, pool, rho, s);
+        case 4: return aux_c<T, 4>(b, what, pool, rho, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_aux(vdwlb_batch& b, int what, void* pool, void* rho, hipStream_t s) {
+    return b.dtype == VDWLB_F64 ? aux_t<double>(b, what, pool, rho, s) : aux_t<float>(b, what, pool, rho, s);
+}
+
+template <int C>
+void fill_instances(vdwlb_batch& b, const std::vector<vdwlb_plan>& plans, std::vector<char>& bytes) {
+    bytes.assign(sizeof(Instance<C>) * b.n, 0);
+    Instance<C>* I = reinterpret_cast<Instance<C>*>(bytes.data());
+    for (int k = 0; k < b.n; ++k) {
+        const vdwlb_plan& p = plans[k];
+        // the periodic-wrap mode depends on the strip width and is set in the kernel
+        I[k].g = make_geometry(p, 32, b.ny);
+        I[k].g.band_w = 0;
+        I[k].offset = b.offset[k];
+        I[k].rho_offset = b.rho_offset[k];
+        I[k].k = make_coeffs<C>(p);
+    }
+}
+
+int device_blocks(const vdwlb_batch& b) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const int per_cu = (b.threads == 1024 && b.ny >= 4) ? 1 : 4;
+    return cus * per_cu;
+}
+
+void release_batch_graph(vdwlb_batch& b) {
+    if (b.graph) (void)hipGraphExecDestroy(b.graph);
+    b.graph = nullptr;
+    b.gA = b.gB = nullptr;
+    b.gsteps = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch** out) {
+    if (!out) return VDWLB_E_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || !descs) return VDWLB_E_INVALID_ARG;
+    std::vector<vdwlb_plan*> tmp(n, nullptr);
+    std::vector<vdwlb_plan> plans;
+    plans.reserve(n);
+    const int C = descs[0].ncomp, dtype = descs[0].dtype, ny = descs[0].ny;
+    for (int k = 0; k < n; ++k) {
+        if (descs[k].ncomp != C || descs[k].dtype != dtype || descs[k].ny != ny) return VDWLB_E_INVALID_ARG;
+    }
+    // Validate every description with the plan rules, on host data only.
+    for (int k = 0; k < n; ++k) {
+        vdwlb_status st = validate_desc(&descs[k]);
+        if (st != VDWLB_OK) return st;
+        plans.push_back(plan_from_desc(descs[k]));
+    }
+    if (ny != 1 && ny != 2 && ny != 4 && ny != 8) return VDWLB_E_UNSUPPORTED;
+
+    vdwlb_batch* b = new (std::nothrow) vdwlb_batch();
+    if (!b) return VDWLB_E_DEVICE;
+    b->n = n;
+    b->C = C;
+    b->dtype = dtype;
+    b->ny = ny;
+    b->offset.resize(n);
+    b->rho_offset.resize(n);
+    b->sites.resize(n);
+    int64_t off = 0, roff = 0;
+    for (int k = 0; k < n; ++k) {
+        b->offset[k] = off;
+        b->rho_offset[k] = roff;
+        b->sites[k] = (int64_t)plans[k].nx * plans[k].ny;
+        off += (int64_t)Q * C * plans[k].plane;
+        roff += (int64_t)C * b->sites[k];
+    }
+    b->pool_elems = off;
+    b->rho_elems = roff;
+    std::vector<char> bytes;
+    switch (C) {
+        case 1: fill_instances<1>(*b, plans, bytes); break;
+        case 2: fill_instances<2>(*b, plans, bytes); break;
+        case 3: fill_instances<3>(*b, plans, bytes); break;
+        default: fill_instances<4>(*b, plans, bytes); break;
+    }
+    // Longest processing time first: largest instances at the head of the queue.
+    std::vector<int> order(n);
+    for (int k = 0; k < n; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return b->sites[i] > b->sites[j]; });
+    hipError_t e = hipMalloc(&b->d_inst, bytes.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_order, sizeof(int) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(int) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counter, 256);
+    if (e == hipSuccess) e = hipMemcpy(b->d_inst, bytes.data(), bytes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_status, 0, sizeof(int) * n);
+    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 256);
+    if (e != hipSuccess) {
+        vdwlb_batch_destroy(b);
+        return bfail(e, "batch device buffers");
+    }
+    *out = b;
+    return VDWLB_OK;
+}
+
+vdwlb_status vdwlb_batch_destroy(vdwlb_batch* b) {
+    if (!b) return VDWLB_OK;
+    release_batch_graph(*b);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_status) (void)hipFree(b->d_status);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+    return VDWLB_OK;
+}
+
+size_t vdwlb_batch_state_bytes(const vdwlb_batch* b) {
+    return b ? (size_t)b->pool_elems * (b->dtype == VDWLB_F64 ? 8 : 4) : 0;
+}
+
+int64_t vdwlb_batch_offset(const vdwlb_batch* b, int32_t k) {
+    return (b && k >= 0 && k < b->n) ? b->offset[k] : -1;
+}
+
+int64_t vdwlb_batch_density_offset(const vdwlb_batch* b, int32_t k) {
+    return (b && k >= 0 && k < b->n) ? b->rho_offset[k] : -1;
+}
+
+vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* b, int32_t threads, int32_t blocks) {
+    if (!b || (threads != 256 && threads != 1024) || blocks < 0) return VDWLB_E_INVALID_ARG;
+    if (threads != b->threads || blocks != b->blocks) release_batch_graph(*b);
+    b->threads = threads;
+    b->blocks = blocks;
+    return VDWLB_OK;
+}
+
+vdwlb_status vdwlb_batch_init(vdwlb_batch* b, void* pool, const void* rho, void* stream) {
+    if (!b || !pool || !rho) return VDWLB_E_INVALID_ARG;
+    hipError_t e = batch_aux(*b, 0, pool, const_cast<void*>(rho), (hipStream_t)stream);
+    return e == hipSuccess ? VDWLB_OK : bfail(e, "batch init");
+}
+
+vdwlb_status vdwlb_batch_density(vdwlb_batch* b, const void* pool, void* rho, void* stream) {
+    if (!b || !pool || !rho) return VDWLB_E_INVALID_ARG;
+    hipError_t e = batch_aux(*b, 1, const_cast<void*>(pool), rho, (hipStream_t)stream);
+    return e == hipSuccess ? VDWLB_OK : bfail(e, "batch density");
+}
+
+vdwlb_status vdwlb_batch_run(vdwlb_batch* b, void* poolA, void* poolB, int64_t nsteps, void* stream,
+                             int32_t* out_which) {
+    if (!b || !poolA || !poolB || poolA == poolB || nsteps < 0 || nsteps > 0x7fffffff) return VDWLB_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int blocks = b->blocks > 0 ? b->blocks : device_blocks(*b);
+    if (blocks > b->n) blocks = b->n;
+    if (!(b->graph && b->gA == poolA && b->gB == poolB && b->gsteps == nsteps && b->gblocks == blocks &&
+          b->gthreads == b->threads)) {
+        release_batch_graph(*b);
+        hipError_t e = hipSuccess;
+        if (!b->capture_stream) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return bfail(e, "batch capture");
+        hipError_t le = launch_batch(*b, poolA, poolB, (int)nsteps, blocks, b->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->capture_stream, &g);
+        if (le != hipSuccess || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(le != hipSuccess ? le : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->graph = nullptr;
+            return bfail(e, "batch graph instantiate");
+        }
+        b->gA = poolA;
+        b->gB = poolB;
+        b->gsteps = nsteps;
+        b->gblocks = blocks;
+        b->gthreads = b->threads;
+    }
+    hipError_t e = hipGraphLaunch(b->graph, s);
+    if (e != hipSuccess) return bfail(e, "batch graph launch");
+    if (out_which) *out_which = (int32_t)(nsteps & 1);
+    return VDWLB_OK;
+}
+
+vdwlb_status vdwlb_batch_status(vdwlb_batch* b, int32_t* per_instance, void* stream) {
+    if (!b) return VDWLB_E_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return bfail(e, "batch status");
+    std::vector<int32_t> st(b->n);
+    e = hipMemcpy(st.data(), b->d_status, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bfail(e, "batch status");
+    if (per_instance) std::memcpy(per_instance, st.data(), sizeof(int32_t) * b->n);
+    for (int k = 0; k < b->n; ++k)
+        if (st[k]) return VDWLB_E_UNPHYSICAL;
+    return VDWLB_OK;
+}
+
+}  // extern "C"

@@ -6,6 +6,8 @@
 
 #include <vector>
 
+#include "../../include/vdwlb.h"
+
 struct vdwlb_plan {
     int dim = 2, nx = 0, ny = 0, C = 0, dtype = 0, force = 0;
     double kT = 0, tau = 1, gamma = 1;
@@ -14,6 +16,7 @@ struct vdwlb_plan {
     int device = 0;
     int* d_flag = nullptr;  // sticky unphysical-state flag (device)
     int sched = 0;          // index into the schedule table
+    int map_mode = 0;       // workgroup -> tile order: 0 row-major ranges, 1 vertical XCD bands
     // captured step sequence, bound to one (fA, fB) pair and schedule
     hipGraphExec_t graph = nullptr;
     const void* gA = nullptr;
@@ -29,7 +32,8 @@ constexpr int GRAPH_PAIRS = 16;
 
 struct Schedule {
     int tx, ty;
-    bool reload, nt;
+    bool nt;
+    int occ;
 };
 
 int schedule_count();
@@ -47,5 +51,9 @@ int32_t ensure_graph(vdwlb_plan& p, const void* fA, const void* fB);
 void release_graph(vdwlb_plan& p);
 
 bool maxwell_coexistence(double a, double b, double kT, double* rho_gas, double* rho_liquid);
+
+int32_t validate_desc(const vdwlb_desc* d);
+vdwlb_plan plan_from_desc(const vdwlb_desc& d);
+int32_t set_device_error(hipError_t e, const char* where);
 
 }  // namespace vdwlb

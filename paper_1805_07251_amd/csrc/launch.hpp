@@ -6,25 +6,25 @@
 
 namespace vdwlb {
 
-// Tile schedules of the sweep (TX x TY sites per workgroup, reload, NT
-// stores); the autotuner picks one per plan.
-#define VDWLB_SCHEDULES(X)          \
-    X(0, 64, 4, false, false)       \
-    X(1, 64, 8, false, false)       \
-    X(2, 32, 8, false, false)       \
-    X(3, 64, 16, false, false)      \
-    X(4, 128, 4, false, false)      \
-    X(5, 32, 16, false, false)      \
-    X(6, 64, 8, true, false)        \
-    X(7, 32, 16, true, false)       \
-    X(8, 64, 16, true, false)       \
-    X(9, 128, 4, true, false)       \
-    X(10, 64, 8, false, true)       \
-    X(11, 32, 16, false, true)      \
-    X(12, 64, 8, true, true)        \
-    X(13, 32, 16, true, true)
+// Tile schedules of the sweep (TX x TY sites per workgroup, non-temporal
+// stores, minimum waves per SIMD); the autotuner picks one per plan.
+#define VDWLB_SCHEDULES(X)     \
+    X(0, 64, 4, false, 0)      \
+    X(1, 64, 8, false, 0)      \
+    X(2, 32, 8, false, 0)      \
+    X(3, 64, 16, false, 0)     \
+    X(4, 128, 4, false, 0)     \
+    X(5, 32, 16, false, 0)     \
+    X(6, 64, 8, true, 0)       \
+    X(7, 32, 16, true, 0)      \
+    X(8, 32, 32, true, 0)      \
+    X(9, 128, 4, true, 0)      \
+    X(10, 64, 8, true, 5)      \
+    X(11, 32, 16, true, 5)     \
+    X(12, 32, 16, true, 6)     \
+    X(13, 64, 8, true, 6)
 
-#define VDWLB_SCHED_ENTRY(i, tx, ty, rl, nt) {tx, ty, rl, nt},
+#define VDWLB_SCHED_ENTRY(i, tx, ty, nt, occ) {tx, ty, nt, occ},
 constexpr Schedule SCHEDULES[] = {VDWLB_SCHEDULES(VDWLB_SCHED_ENTRY)};
 #undef VDWLB_SCHED_ENTRY
 constexpr int N_SCHEDULES = sizeof(SCHEDULES) / sizeof(SCHEDULES[0]);
@@ -38,6 +38,7 @@ inline Geometry make_geometry(const vdwlb_plan& p, int tx, int ty) {
     // single-step wrapping needs every index to overshoot an extent by less
     // than the extent itself: tile overhang plus a radius-3 reach
     g.wrap_general = (p.nx < tx + 8 || p.ny < ty + 8) ? 1 : 0;
+    g.band_w = (p.map_mode == 1 && g.tiles_x % 8 == 0) ? g.tiles_x / 8 : 0;
     return g;
 }
 
@@ -61,12 +62,12 @@ Coeffs<C> make_coeffs(const vdwlb_plan& p) {
     return k;
 }
 
-template <typename T, int C, int TX, int TY, bool RL, bool NTS>
+template <typename T, int C, int TX, int TY, bool NTS, int OCC>
 hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
     const Geometry g = make_geometry(p, TX, TY);
     const Coeffs<C> k = make_coeffs<C>(p);
     const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_sweep<T, C, TX, TY, RL, NTS>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin, (T*)fout, g, k,
+    hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin, (T*)fout, g, k,
                        p.d_flag);
     return hipGetLastError();
 }
@@ -74,8 +75,8 @@ hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream
 template <typename T, int C>
 hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
     switch (p.sched) {
-#define VDWLB_SCHED_CASE(i, tx, ty, rl, nt) \
-    case i: return run_sweep<T, C, tx, ty, rl, nt>(p, fin, fout, s);
+#define VDWLB_SCHED_CASE(i, tx, ty, nt, occ) \
+    case i: return run_sweep<T, C, tx, ty, nt, occ>(p, fin, fout, s);
         VDWLB_SCHEDULES(VDWLB_SCHED_CASE)
 #undef VDWLB_SCHED_CASE
         default: return hipErrorInvalidValue;

@@ -34,6 +34,7 @@ struct Geometry {
     int64_t plane;     // elements between (c, i) planes
     int tiles_x;       // tiles along x
     int wrap_general;  // extents too small for single-step periodic wrapping
+    int band_w;        // > 0: XCD k owns the vertical band of band_w tile columns
 };
 
 // Coefficients of one lattice, precomputed on the host in double.
@@ -53,13 +54,23 @@ struct Coeffs {
 
 constexpr double THETA = 1.0 / 3.0;
 
-// The hardware hands consecutive workgroup ids to the 8 XCDs in turn.  Give
-// each XCD a contiguous range of tiles so that tiles that share halos run on
-// the same XCD (and L2) at about the same time.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
+// The hardware hands consecutive workgroup ids to the 8 XCDs in turn.  Map
+// them so that tiles that share halos run on the same XCD (and L2) at about
+// the same time: either each XCD takes a contiguous range of row-major tiles
+// (a horizontal band), or (band_w > 0) XCD k takes the vertical band of
+// tile columns [k band_w, (k+1) band_w) and walks it row by row.
+__device__ __forceinline__ void xcd_tile(int b, int n, const Geometry& g, int& tx, int& ty) {
     const int xcd = b & 7, k = b >> 3;
-    const int q = n >> 3, r = n & 7;
-    return xcd * q + (xcd < r ? xcd : r) + k;
+    if (g.band_w > 0) {
+        const int r = k / g.band_w;
+        tx = xcd * g.band_w + (k - r * g.band_w);
+        ty = r;
+        return;
+    }
+    const int q = n >> 3, rr = n & 7;
+    const int t = xcd * q + (xcd < rr ? xcd : rr) + k;
+    ty = t / g.tiles_x;
+    tx = t - ty * g.tiles_x;
 }
 
 __device__ __forceinline__ int wrapc(int v, int n, int general) {
@@ -113,7 +124,7 @@ __device__ __forceinline__ void momentum(const T (&p)[Q], T& jx, T& jy) {
 // (ex, ey): gradient 3 sum_i w_i v_i g(x + v_i) and Laplacian
 // 6 sum_i w_i (g(x + v_i) - g(x)).
 template <typename T, int S>
-__device__ __forceinline__ T lap9(const T* a, int ex, int ey) {
+__device__ __forceinline__ T lap9s(const T* a, int ex, int ey) {
     const T* r0 = a + ey * S + ex;
     const T axis = (r0[1] + r0[-1]) + (r0[S] + r0[-S]);
     const T diag = (r0[S + 1] + r0[S - 1]) + (r0[-S - 1] + r0[-S + 1]);
@@ -121,7 +132,7 @@ __device__ __forceinline__ T lap9(const T* a, int ex, int ey) {
 }
 
 template <typename T, int S>
-__device__ __forceinline__ void grad9(const T* a, int ex, int ey, T& gx, T& gy) {
+__device__ __forceinline__ void grad9s(const T* a, int ex, int ey, T& gx, T& gy) {
     const T* r0 = a + ey * S + ex;
     const T ne = r0[S + 1], nw = r0[S - 1], sw = r0[-S - 1], se = r0[-S + 1];
     gx = (T(4) * (r0[1] - r0[-1]) + ((ne - nw) + (se - sw))) * T(1.0 / 12.0);
@@ -150,17 +161,15 @@ __device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], 
     }
     const T free_vol = T(1) - eta;
     const T inv = T(1) / free_vol;
-    const T lfree = dlog(free_vol);
     bool ok = free_vol > T(0);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         ok = ok && rho[c] > T(0);
-        const T lr = dlog(rho[c]);
-        T mu = T(k.kT) * ((lr - lfree) + T(k.b[c]) * tot * inv);
+        T mu = T(k.kT) * (dlog(rho[c] * inv) + T(k.b[c]) * tot * inv);
 #pragma unroll
         for (int d = 0; d < C; ++d) mu -= T(k.a2[c][d]) * rho[d] + T(k.kap[c][d]) * lap[d];
         phi[c] = T(k.gamma) * mu;
-        if (k.force == 1) phi[c] -= T(THETA) * lr;
+        if (k.force == 1) phi[c] -= T(THETA) * dlog(rho[c]);
         ok = ok && finite_val(phi[c]);
     }
     return ok;
@@ -267,26 +276,162 @@ __device__ __forceinline__ void ring_coords(int r, int& ex, int& ey) {
     }
 }
 
-// RELOAD: keep only rho and j of the interior site across the two barriers
-// and pull the populations of each component again right before its
-// collision (fewer live VGPRs, more waves per SIMD; the second read hits L2).  NTSTORE: non-temporal stores of the new
-// state, so that output lines do not displace halo lines in L2.
-template <typename T, int C, int TX, int TY, bool RELOAD, bool NTSTORE>
-__global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g,
-                                                    Coeffs<C> k, int* __restrict__ flag) {
+// Density of one site from the populations pulled into it, written to LDS
+// (component c at dst[c * stride]).
+template <typename T, int C>
+__device__ __forceinline__ void pull_density(const T* __restrict__ f, const Geometry& g, int x, int y, T* dst,
+                                             int stride) {
+    int o[Q];
+    pull_offsets(g, x, y, o);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T q[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) q[i] = f[(int64_t)(c * Q + i) * g.plane + o[i]];
+        dst[c * stride] = density<T>(q);
+    }
+}
+
+// Friction, collision and store of one site whose pulled populations p,
+// density, momentum, mean-field force g and density Laplacian are known.
+template <typename T, int C, bool NTSTORE>
+__device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T (&jx)[C], T (&jy)[C], T (&gx)[C],
+                                              T (&gy)[C], const T (&lap)[C], const Coeffs<C>& k,
+                                              T* __restrict__ fout, int64_t plane, int s) {
+    if constexpr (C > 1) {
+        T W[C][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = 0; d < C; ++d)
+                W[c][d] = c == d ? T(0) : T(k.lam[c][d]) * rho[c] * rho[d] / (rho[c] + rho[d]);
+        friction<T, C>(rho, jx, gx, W);
+        friction<T, C>(rho, jy, gy, W);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        collide<T>(p[c], rho[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T* dst = fout + (int64_t)(c * Q + i) * plane + s;
+            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], dst);
+            else *dst = p[c][i];
+        }
+    }
+}
+
+// LDS footprint of one full-height strip: the NY rows of the lattice at rows
+// 1..NY, a copy of the last lattice row at row 0 and of the first at row
+// NY + 1, so the periodic y neighbours sit at fixed strides; TX
+// columns plus an x ring of 2 (density) / 1 (potential).
+template <int TX, int NY>
+struct StripLds {
+    static constexpr int EX = TX + 4, MX = TX + 2, RY = NY + 2;
+    static constexpr int SR = EX * RY, SP = MX * RY;
+};
+
+// Store v at padded row `row` (1..NY) of column e, and at its periodic copy.
+template <typename T, int NY, int S>
+__device__ __forceinline__ void put_wrapped(T* plane, int row, int e, T v) {
+    plane[row * S + e] = v;
+    if (row == 1) plane[(NY + 1) * S + e] = v;
+    if (row == NY) plane[e] = v;
+}
+
+// One time step of the TX-column strip starting at x0 of a lattice whose
+// height is exactly NY (quasi-1-D lattices): the rows wrap inside LDS, so
+// only the x ring is recomputed.  Executed by TX * NY threads.  Every site
+// goes through the same arithmetic as in the plain sweep (same functions and
+// stencil expressions), so results are bit-identical to it.
+template <typename T, int C, int TX, int NY, bool NTSTORE>
+__device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restrict__ fout, const Geometry& g,
+                                           const Coeffs<C>& k, int x0, T* s_rho, T* s_phi) {
+    using L = StripLds<TX, NY>;
+    constexpr int NT = TX * NY, EX = L::EX, MX = L::MX;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx;
+    const int xs = wrapc(x, g.nx, g.wrap_general);
+
+    T p[C][Q];
+    int o[Q];
+    pull_offsets(g, xs, ly, o);
+    pull<T, C>(fin, g, o, p);
+    T rho[C], jx[C], jy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = density<T>(p[c]);
+        momentum<T>(p[c], jx[c], jy[c]);
+        put_wrapped<T, NY, EX>(s_rho + c * L::SR, ly + 1, lx + 2, rho[c]);
+    }
+    for (int r = threadIdx.x; r < 4 * NY; r += NT) {
+        const int row = r >> 2, kq = r & 3;
+        const int ex = kq < 2 ? kq : EX - 4 + kq;
+        T q[C];
+        pull_density<T, C>(fin, g, wrapc(x0 - 2 + ex, g.nx, g.wrap_general), row, q, 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) put_wrapped<T, NY, EX>(s_rho + c * L::SR, row + 1, ex, q[c]);
+    }
+    __syncthreads();
+
+    bool bad = false;
+    for (int m = threadIdx.x; m < MX * NY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        T r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c * L::SR + (my + 1) * EX + mx + 1];
+            l[c] = lap9s<T, EX>(s_rho + c * L::SR, mx + 1, my + 1);
+        }
+        bad |= !potential<T, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) put_wrapped<T, NY, MX>(s_phi + c * L::SP, my + 1, mx, ph[c]);
+    }
+    __syncthreads();
+
+    if (x < g.nx) {
+        T gx[C], gy[C], lap[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T px, py, rx, ry;
+            grad9s<T, MX>(s_phi + c * L::SP, lx + 1, ly + 1, px, py);
+            grad9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1, rx, ry);
+            lap[c] = lap9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1);
+            gx[c] = -rho[c] * px;
+            gy[c] = -rho[c] * py;
+            if (k.force == 0) {
+                gx[c] += T(THETA) * rx;
+                gy[c] += T(THETA) * ry;
+            }
+        }
+        collide_store<T, C, NTSTORE>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, ly * g.nx + x);
+    }
+    return bad;
+}
+
+// The plain sweep: one launch per time step, one workgroup per TX x TY tile.
+// Phase 1 pulls the 9C populations of each interior site into registers
+// (reused by the collision) and the densities of the radius-2 ring around the
+// tile (re-read from L2/MALL, never stored) into LDS; phase 2 evaluates the
+// potential on the tile plus a radius-1 ring; phase 3 takes gradients and the
+// Laplacian from LDS and collides.
+// NTSTORE: non-temporal stores of the new state, so that output lines do not
+// displace halo lines in L2.  OCC > 0 asks the compiler for at least OCC waves
+// per SIMD (a VGPR budget of 512 / OCC).
+template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k, int* __restrict__ flag) {
     constexpr int NT = TX * TY, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
     constexpr int RING = EX * EY - TX * TY;
     __shared__ T s_rho[C][EY * EX];
     __shared__ T s_phi[C][MY * MX];
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int ty_ = tile / g.tiles_x;
-    const int x0 = (tile - ty_ * g.tiles_x) * TX, y0 = ty_ * TY;
+    int tx_, ty_;
+    xcd_tile(blockIdx.x, gridDim.x, g, tx_, ty_);
+    const int x0 = tx_ * TX, y0 = ty_ * TY;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const int x = x0 + lx, y = y0 + ly;
     const int xs = wrapc(x, g.nx, g.wrap_general), ys = wrapc(y, g.ny, g.wrap_general);
 
-    // Phase 1: interior populations and densities.
     T p[C][Q];
     int o[Q];
     pull_offsets(g, xs, ys, o);
@@ -298,24 +443,14 @@ __global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T*
         momentum<T>(p[c], jx[c], jy[c]);
         s_rho[c][(ly + 2) * EX + lx + 2] = rho[c];
     }
-    // Densities of the radius-2 ring around the tile.
     for (int r = threadIdx.x; r < RING; r += NT) {
         int ex, ey;
         ring_coords<TX, TY>(r, ex, ey);
-        const int hx = wrapc(x0 - 2 + ex, g.nx, g.wrap_general), hy = wrapc(y0 - 2 + ey, g.ny, g.wrap_general);
-        int oh[Q];
-        pull_offsets(g, hx, hy, oh);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            T q[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) q[i] = fin[(int64_t)(c * Q + i) * g.plane + oh[i]];
-            s_rho[c][ey * EX + ex] = density<T>(q);
-        }
+        pull_density<T, C>(fin, g, wrapc(x0 - 2 + ex, g.nx, g.wrap_general), wrapc(y0 - 2 + ey, g.ny, g.wrap_general),
+                           &s_rho[0][ey * EX + ex], EY * EX);
     }
     __syncthreads();
 
-    // Phase 2: potential on the tile plus a radius-1 ring.
     bool bad = false;
     for (int m = threadIdx.x; m < MX * MY; m += NT) {
         const int my = m / MX, mx = m - my * MX;
@@ -323,7 +458,7 @@ __global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T*
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             r[c] = s_rho[c][(my + 1) * EX + mx + 1];
-            l[c] = lap9<T, EX>(s_rho[c], mx + 1, my + 1);
+            l[c] = lap9s<T, EX>(s_rho[c], mx + 1, my + 1);
         }
         bad |= !potential<T, C>(r, l, k, ph);
 #pragma unroll
@@ -332,15 +467,14 @@ __global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T*
     if (bad) atomicOr(flag, 1);
     __syncthreads();
 
-    // Phase 3: force, friction, collision, store.
     if (x >= g.nx || y >= g.ny) return;
     T gx[C], gy[C], lap[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         T px, py, rx, ry;
-        grad9<T, MX>(s_phi[c], lx + 1, ly + 1, px, py);
-        grad9<T, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
-        lap[c] = lap9<T, EX>(s_rho[c], lx + 2, ly + 2);
+        grad9s<T, MX>(s_phi[c], lx + 1, ly + 1, px, py);
+        grad9s<T, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
+        lap[c] = lap9s<T, EX>(s_rho[c], lx + 2, ly + 2);
         gx[c] = -rho[c] * px;
         gy[c] = -rho[c] * py;
         if (k.force == 0) {
@@ -348,31 +482,7 @@ __global__ void __launch_bounds__(TX * TY) k_sweep(const T* __restrict__ fin, T*
             gy[c] += T(THETA) * ry;
         }
     }
-    if constexpr (C > 1) {
-        T W[C][C];
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int d = 0; d < C; ++d)
-                W[c][d] = c == d ? T(0) : T(k.lam[c][d]) * rho[c] * rho[d] / (rho[c] + rho[d]);
-        friction<T, C>(rho, jx, gx, W);
-        friction<T, C>(rho, jy, gy, W);
-    }
-    const int s = y * g.nx + x;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        if constexpr (RELOAD) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) p[c][i] = fin[(int64_t)(c * Q + i) * g.plane + o[i]];
-        }
-        collide<T>(p[c], rho[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T* dst = fout + (int64_t)(c * Q + i) * g.plane + s;
-            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], dst);
-            else *dst = p[c][i];
-        }
-    }
+    collide_store<T, C, NTSTORE>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, y * g.nx + x);
 }
 
 // f_i^c = f^0_i(rho^c, u^c) (Eq. feq).

@@ -17,6 +17,7 @@ long runs, Sec. VI, and the 2-D extension it announces in Sec. VII):
                    b_i in [0.08, 0.12], Dirichlet(1,1,1,1) composition at
                    total density 0.4 / b_mean
   batch_slabs      many quasi-1-D L x 4 lattices with a tanh liquid slab
+                   (bulk densities from a caller-supplied coexistence solver)
   adjoint_case     256x256, spinodal_small parameters plus a smooth target
 """
 from __future__ import annotations
@@ -138,12 +139,22 @@ def batch_draws(seed: int = 0, n: int = 1024, lmin: int = 128, lmax: int = 1024)
     return SlabDraw(L, t, xbar, nu)
 
 
+def one_fluid_a(xbar: float, nu: float) -> float:
+    """Attraction of the one-fluid approximation of a binary mixture of mole
+    fraction xbar: sum_cd x_c x_d a^{cd} with a^{12} = nu a^{11} = nu a^{22}.
+    Callers use it to pick the bulk densities of the initial slab."""
+    return A11 * (xbar * xbar + (1.0 - xbar) ** 2 + 2.0 * nu * xbar * (1.0 - xbar))
+
+
 def slab_instance(L: int, ny: int, t: float, xbar: float, nu: float, rho_gas: float, rho_liq: float,
                   width: float = 2.0) -> Workload:
     """One quasi-1-D lattice: a liquid slab between x = L/4 and 3L/4 with tanh
     edges of the given width (Sec. V initialises with tanh profiles), bulk
     total densities rho_liq / rho_gas supplied by the caller, uniform mole
-    fraction xbar, y-uniform."""
+    fraction xbar, y-uniform.  gamma_mu is half the value of the rule
+    c_s^2 = 1 - 4 kappa rho_l gamma_mu (Eq. kappaGammaMuRelation): Sec. VI.A
+    lowers gamma_mu by factors of 2 to 10 for runs that are unstable at the
+    rule's value."""
     a = np.array([[A11, nu * A11], [nu * A11, A11]])
     b = np.array([B1, B1])
     x = np.arange(L) + 0.5
@@ -151,9 +162,25 @@ def slab_instance(L: int, ny: int, t: float, xbar: float, nu: float, rho_gas: fl
     rho = np.empty((2, ny, L))
     rho[0] = (xbar * tot)[None, :]
     rho[1] = ((1.0 - xbar) * tot)[None, :]
-    # gamma_mu from c_s^2 = 1 - 4 kappa rho_l gamma_mu (Eq. kappaGammaMuRelation)
-    gamma = (1.0 - 1.0 / 3.0) / (4.0 * KAPPA * rho_liq)
+    gamma = 0.5 * (1.0 - 1.0 / 3.0) / (4.0 * KAPPA * rho_liq)
     return Workload(L, ny, t * KT_CRIT, a, b, kappa_matrix(a), rho, gamma_mu=gamma, name=f"slab L={L}")
+
+
+def batch_slabs(maxwell, seed: int = 0, n: int = 1024, ny: int = 4, idx=None, lmax=None):
+    """The batched phase-diagram workload: n quasi-1-D L x ny lattices with L
+    uniform in [128, 1024], kT in [0.6, 1.0] kT_crit, mole fraction in
+    [0.05, 0.95] and a12/a11 in [0.6, 1.2], each initialised with a liquid
+    slab.  maxwell(a, b, kT) -> (rho_gas, rho_liquid) or None supplies the
+    bulk densities of the one-fluid approximation of each mixture (uniform
+    density 0.5 / b when it is above its critical temperature)."""
+    d = batch_draws(seed, n)
+    out = []
+    for k in (range(n) if idx is None else idx):
+        L = int(d.L[k]) if lmax is None else int(min(d.L[k], lmax))
+        m = maxwell(one_fluid_a(d.xbar[k], d.nu[k]), B1, d.t[k] * KT_CRIT)
+        rg, rl = m if m else (0.5 / B1, 0.5 / B1)
+        out.append(slab_instance(L, ny, d.t[k], d.xbar[k], d.nu[k], rg, rl))
+    return out
 
 
 def adjoint_case(seed: int = 0, n: int = 256):

@@ -56,6 +56,20 @@ _SIGS = {
     "vdwlb_autotune": (ctypes.c_int32, [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)]),
     "vdwlb_maxwell": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p, _c_double_p]),
     "vdwlb_copy": (ctypes.c_int32, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "vdwlb_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(Desc), ctypes.POINTER(_VP)]),
+    "vdwlb_batch_destroy": (ctypes.c_int32, [_VP]),
+    "vdwlb_batch_state_bytes": (ctypes.c_size_t, [_VP]),
+    "vdwlb_batch_offset": (ctypes.c_int64, [_VP, ctypes.c_int32]),
+    "vdwlb_batch_density_offset": (ctypes.c_int64, [_VP, ctypes.c_int32]),
+    "vdwlb_batch_set_launch": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "vdwlb_batch_init": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
+    "vdwlb_batch_density": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
+    "vdwlb_batch_run": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_int32)]),
+    "vdwlb_batch_status": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int32), _VP]),
+    "vdwlb_adjoint_param_count": (ctypes.c_int32, [_VP]),
+    "vdwlb_adjoint_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int32]),
+    "vdwlb_moments_adjoint": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP]),
+    "vdwlb_adjoint_segment": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
 }
 
 _lib = None

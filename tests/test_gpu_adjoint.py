@@ -1,0 +1,202 @@
+"""GPU tests of the hand-written adjoint through the C-ABI.
+
+The reference derivatives come from the complex build of the CPU oracle
+(complex step, Squire & Trapp 1998): Im(step(f + i h v)) / h is the exact
+Jacobian-vector product of one step up to round-off, with no subtraction
+error.  Checks:
+  - dot-product test per step: <J v, w> (oracle) = <v, J^T w> (GPU), also for
+    the parameter block, for C = 1, 2, log and nid forcing, tau != 1;
+  - gradients of a density-profile loss through many steps with segment
+    checkpointing against the oracle's complex-step gradient;
+  - the benchmark's 256 x 256, 2000-step case against central finite
+    differences of the GPU forward (h = 1e-6).
+"""
+import numpy as np
+import pytest
+
+from paper_1805_07251_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A11, B1 = I.A11, I.B1
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import adjoint, lattice
+    from paper_1805_07251_amd import vdwlb as V
+
+    return adjoint, lattice, V
+
+
+def mixture(C, nu=0.9, t=0.8, tau=1.0, force=0, lam=0.7, gamma=0.25):
+    a = np.full((C, C), nu * A11)
+    np.fill_diagonal(a, A11)
+    kap = np.full((C, C), 0.1 * nu)
+    np.fill_diagonal(kap, 0.1)
+    return dict(kT=t * I.KT_CRIT, a=a, b=np.full(C, B1), kappa=kap, tau=tau, gamma_mu=gamma,
+                lam=np.full((C, C), lam), force=force)
+
+
+def oracle_lattice(orc, P, nx, ny, cx=False):
+    p = orc.Params(P["kT"], P["a"], P["b"], P["kappa"], tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"],
+                   force=P["force"])
+    return orc.Lattice(p, 2, nx, ny, complex_step=cx)
+
+
+def make_state(orc, P, nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    C = len(P["b"])
+    rho = (5.25 / C) * (1 + 0.05 * rng.uniform(-1, 1, (C, ny, nx)))
+    lat = oracle_lattice(orc, P, nx, ny)
+    lat.init(rho)
+    lat.run(2)
+    return lat.f * (1 + 0.02 * rng.standard_normal(lat.f.shape))
+
+
+def pad(t_np, plane):
+    C, Q, ny, nx = t_np.shape
+    out = np.zeros((C, Q, plane))
+    out[:, :, :nx * ny] = t_np.reshape(C, Q, nx * ny)
+    return torch.as_tensor(out.reshape(-1), device="cuda")
+
+
+def unpad(t, C, ny, nx, plane):
+    return t.view(C, 9, plane)[:, :, :nx * ny].reshape(C, 9, ny, nx).cpu().numpy()
+
+
+def gpu_vjp(lattice, V, P, f, wbar, nsteps=1):
+    C, _, ny, nx = f.shape
+    plan = lattice.Plan(nx, ny, P["kT"], P["a"], P["b"], P["kappa"], P["tau"], P["gamma_mu"], P["lam"], "f64",
+                        P["force"])
+    fa, fb = pad(f, plan.plane), pad(wbar, plan.plane)
+    ws = torch.empty(int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, nsteps)) // 8 + 1,
+                     dtype=torch.float64, device="cuda")
+    pbar = torch.zeros(int(V.lib().vdwlb_adjoint_param_count(plan.handle)), dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    V.check(V.lib().vdwlb_adjoint_segment(plan.handle, fa.data_ptr(), nsteps, fb.data_ptr(), ws.data_ptr(),
+                                          pbar.data_ptr(), s))
+    torch.cuda.synchronize()
+    return unpad(fb, C, ny, nx, plan.plane), pbar.cpu().numpy()
+
+
+def oracle_param_dirs(C):
+    """Complex-step directions in the oracle's parameter vector
+    [kT, a (C x C), b, kappa (C x C)] matching the adjoint's cotangent order
+    [kT, a^{cd} (c <= d), b, kappa^{cd} (c <= d)]."""
+    n = 1 + 2 * C * C + C
+    dirs = [np.eye(n)[0]]
+    for base in (1,):
+        for c in range(C):
+            for d in range(c, C):
+                v = np.zeros(n)
+                v[base + c * C + d] = 1
+                v[base + d * C + c] = 1
+                dirs.append(v)
+    for c in range(C):
+        v = np.zeros(n)
+        v[1 + C * C + c] = 1
+        dirs.append(v)
+    for c in range(C):
+        for d in range(c, C):
+            v = np.zeros(n)
+            v[1 + C * C + C + c * C + d] = 1
+            v[1 + C * C + C + d * C + c] = 1
+            dirs.append(v)
+    return dirs
+
+
+@pytest.mark.parametrize("C,force,tau", [(2, 0, 1.0), (2, 1, 1.0), (2, 0, 0.8), (1, 0, 1.0), (1, 1, 0.9)])
+def test_dot_product_one_step(gpu, orc, C, force, tau):
+    _, lattice, V = gpu
+    P = mixture(C, tau=tau, force=force)
+    nx, ny = 23, 18
+    f = make_state(orc, P, nx, ny, 1)
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(f.shape) * np.abs(f)
+    w = rng.standard_normal(f.shape)
+    h = 1e-20
+    lc = oracle_lattice(orc, P, nx, ny, cx=True)
+    out, st = lc.step_from(f + 1j * h * v)
+    assert st == 0
+    Jv = out.imag / h
+    fb, pbar = gpu_vjp(lattice, V, P, f, w)
+    lhs, rhs = float((Jv * w).sum()), float((v * fb).sum())
+    scale = np.sqrt((Jv**2).sum() * (w**2).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs)
+    # parameter block: <d f'/d theta_k, w> = pbar_k
+    for k, d in enumerate(oracle_param_dirs(C)):
+        lc = oracle_lattice(orc, P, nx, ny, cx=True)
+        lc.prm = lc.prm.astype(np.complex128) + 1j * h * d
+        out, _ = lc.step_from(f.astype(np.complex128))
+        ref = float(((out.imag / h) * w).sum())
+        sc = np.sqrt(((out.imag / h) ** 2).sum() * (w**2).sum())
+        assert abs(pbar[k] - ref) <= 1e-11 * sc + 1e-300, (k, pbar[k], ref)
+
+
+def oracle_theta_grad(orc, P, k_hat, rho0, tgt, nsteps):
+    """Complex-step gradient of sum (rho1_T - tgt)^2 w.r.t. theta = [kT, a
+    pairs, b, kappa] with kappa^{cd} = kappa k_hat^{cd}."""
+    C = len(P["b"])
+    nx, ny = rho0.shape[2], rho0.shape[1]
+    h = 1e-20
+    dirs = oracle_param_dirs(C)
+    na = C * (C + 1) // 2
+    kdir = np.zeros_like(dirs[0])
+    kdir[1 + C * C + C:] = np.asarray(k_hat).reshape(-1)
+    theta_dirs = dirs[: 1 + na + C] + [kdir]
+    g = []
+    for d in theta_dirs:
+        lc = oracle_lattice(orc, P, nx, ny, cx=True)
+        lc.prm = lc.prm.astype(np.complex128) + 1j * h * d
+        lc.init(rho0)
+        lc.run(nsteps)
+        r = lc.moments()[0]
+        g.append((((r[0] - tgt) ** 2).sum()).imag / h)
+    return np.array(g)
+
+
+@pytest.mark.parametrize("C", [1, 2])
+def test_gradient_through_segments_vs_complex_step(gpu, orc, C):
+    adjoint, _, _ = gpu
+    P = mixture(C)
+    k_hat = P["kappa"] / 0.1
+    nx, ny, nsteps = 20, 16, 40
+    rng = np.random.default_rng(3)
+    rho0 = (5.25 / C) * (1 + 0.01 * rng.uniform(-1, 1, (C, ny, nx)))
+    tgt = rho0[0].mean() * (1 + 0.05 * np.cos(2 * np.pi * np.arange(nx) / nx))[None, :].repeat(ny, 0)
+    theta = adjoint.theta_from_params(P["kT"], P["a"], P["b"], 0.1)
+    spec = adjoint.Spec(nx, ny, C, k_hat, nsteps, ckpt=15, tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"])
+    tg = torch.as_tensor(tgt, device="cuda")
+    loss, grad = adjoint.run_and_grad(theta, torch.as_tensor(rho0, device="cuda"), spec,
+                                      lambda r: ((r[0] - tg) ** 2).sum())
+    ref = oracle_theta_grad(orc, P, k_hat, rho0, tgt, nsteps)
+    np.testing.assert_allclose(grad, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_adjoint_case_against_finite_differences(gpu):
+    """256 x 256, 2000 steps, checkpoints every 100: the adjoint gradient of
+    the density-profile loss against central differences (h = 1e-6) of the
+    GPU forward.  The finite difference carries O(h^2) truncation and
+    O(eps / h) round-off, about 1e-5 relative for this loss."""
+    adjoint, _, _ = gpu
+    w, tgt = I.adjoint_case(0)
+    k_hat = w.kappa / I.KAPPA
+    theta = adjoint.theta_from_params(w.kT, w.a, w.b, I.KAPPA)
+    spec = adjoint.Spec(w.nx, w.ny, 2, k_hat, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
+    rho0 = torch.as_tensor(w.rho, device="cuda")
+    tg = torch.as_tensor(tgt, device="cuda")
+    loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
+    loss, grad = adjoint.run_and_grad(theta, rho0, spec, loss_fn)
+    hh = 1e-6
+    for k in range(len(theta)):
+        up, dn = theta.copy(), theta.copy()
+        up[k] += hh
+        dn[k] -= hh
+        lu = float(loss_fn(adjoint.VdwLBFunction.apply(torch.as_tensor(up), rho0, spec)))
+        ld = float(loss_fn(adjoint.VdwLBFunction.apply(torch.as_tensor(dn), rho0, spec)))
+        fd = (lu - ld) / (2 * hh)
+        assert abs(fd - grad[k]) <= 1e-4 * abs(grad[k]) + 1e-6 * np.abs(grad).max(), (k, fd, grad[k])

@@ -1,0 +1,130 @@
+"""GPU tests of the batched sweep (persistent kernel over many quasi-1-D
+lattices) through the C-ABI.
+
+The batch walks each lattice in full-height strips whose rows wrap inside
+LDS, with the same per-site arithmetic as the plain sweep, so every instance
+must match a plain per-instance run bit for bit; small instances are also
+compared with the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+from paper_1805_07251_amd import inputs as I
+
+from ._util import oracle_run, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import batch, lattice
+
+    return batch, lattice
+
+
+def slabs(seed, idx, ny=4, lmax=None):
+    return I.batch_slabs(T.maxwell_single, seed, ny=ny, idx=list(idx), lmax=lmax)
+
+
+def plain_state(lattice, w, nsteps, dtype="f64"):
+    lat = lattice.Lattice.from_workload(w, dtype=dtype)
+    lat.init(w.rho)
+    lat.run(nsteps)
+    return lat.state_sites().cpu().numpy()
+
+
+def batch_run(batch, ws, nsteps, dtype="f64", threads=256, chunks=None):
+    b = batch.Batch(ws, dtype=dtype)
+    b.set_launch(threads, 0)
+    b.init([w.rho for w in ws])
+    for n in chunks or [nsteps]:
+        b.run(n)
+    return b
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_batch_matches_plain_bitwise(gpu, threads):
+    batch, lattice = gpu
+    ws = slabs(0, range(10))
+    b = batch_run(batch, ws, 60, threads=threads)
+    st = b.status()
+    for k, w in enumerate(ws):
+        got = b.state(k).cpu().numpy()
+        ref = plain_state(lattice, w, 60)
+        if st[k] == 0:
+            assert np.array_equal(got, ref), k
+
+
+def test_batch_against_oracle(gpu, orc):
+    batch, _ = gpu
+    ws = slabs(1, range(3), lmax=40)
+    b = batch_run(batch, ws, 30)
+    assert np.all(b.status() == 0)
+    rho = [r.cpu().numpy() for r in b.densities()]
+    for k, w in enumerate(ws):
+        ref, st = oracle_run(orc, w, 30)
+        assert st == 0
+        assert rel_err(rho[k], ref.moments()[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("ny", [1, 2, 8])
+def test_batch_heights(gpu, ny):
+    batch, lattice = gpu
+    ws = slabs(2, range(5), ny=ny, lmax=300)
+    for w in ws:  # break the y-uniformity so the y stencils matter
+        w.rho = w.rho * (1 + 0.005 * np.random.default_rng(ny).uniform(-1, 1, w.rho.shape))
+    b = batch_run(batch, ws, 40)
+    for k, w in enumerate(ws):
+        assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, w, 40)), k
+
+
+def test_batch_f32(gpu):
+    batch, lattice = gpu
+    ws = slabs(3, range(6), lmax=256)
+    b = batch_run(batch, ws, 40, dtype="f32")
+    for k, w in enumerate(ws):
+        assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, w, 40, dtype="f32")), k
+
+
+def test_unphysical_instance_is_isolated(gpu):
+    batch, lattice = gpu
+    ws = slabs(4, range(4), lmax=200)
+    ws[1].rho = ws[1].rho.copy()
+    ws[1].rho[:, :, 10:20] = 12.0  # eta > 1 in a block of instance 1
+    b = batch_run(batch, ws, 25)
+    st = b.status()
+    assert st[1] == 1
+    for k in (0, 2, 3):
+        assert st[k] == 0
+        assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, ws[k], 25)), k
+
+
+def test_split_runs_replay_graph(gpu):
+    """Runs are replayed from a captured graph (queue counter reset by a
+    kernel inside it); 3 x 20 steps equal 60 steps."""
+    batch, _ = gpu
+    ws = slabs(5, range(6), lmax=300)
+    a = batch_run(batch, ws, 0, chunks=[20, 20, 20])
+    b = batch_run(batch, ws, 60)
+    for k in range(len(ws)):
+        assert np.array_equal(a.state(k).cpu().numpy(), b.state(k).cpu().numpy()), k
+
+
+def test_full_batch_sampled(gpu):
+    """The 1024-lattice workload in the benchmark's launch shape: 100 steps,
+    six sampled instances (largest, smallest, random) against plain runs."""
+    batch, lattice = gpu
+    d = I.batch_draws(0)
+    ws = slabs(0, range(len(d.L)))
+    b = batch_run(batch, ws, 100, threads=1024)
+    st = b.status()
+    order = np.argsort(d.L)
+    for k in [int(order[0]), int(order[-1]), 3, 77, 500, 1000]:
+        if st[k] == 0:
+            assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, ws[k], 100)), k
+    assert (st == 0).mean() > 0.9

@@ -70,7 +70,7 @@ def test_spinodal_small_f32_1000_steps(gpu, orc):
     assert rel_err(np_(rho), rho_ref) <= 1e-4
 
 
-N_SCHED = 14
+N_SCHED = 28
 
 
 @pytest.mark.parametrize("sched", range(N_SCHED))
@@ -86,10 +86,25 @@ def test_populations_one_step_every_schedule(gpu, orc, sched):
     np.testing.assert_allclose(f, ref.f, rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("sched", [15, 19, 25])
+def test_band_mapping_against_oracle(gpu, orc, sched):
+    """Vertical XCD bands (schedules 14..27) on a lattice whose tile columns
+    divide by 8."""
+    w = I.spinodal_small(1, n=64)
+    w.nx, w.ny = 512, 37
+    w.rho = np.random.default_rng(13).uniform(2.5, 2.75, (2, 37, 512))
+    ref, _ = oracle_run(orc, w, 3)
+    lat = gpu_run(gpu, w, 3, sched=sched)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-14)
+
+
 def test_schedules_bitwise_identical(gpu):
+    """Every tile shape, kernel variant and workgroup order gives the same
+    bits (512 columns make the vertical XCD bands active for 32- and 64-wide
+    tiles; 70 rows leave ragged tiles)."""
     w = I.spinodal_small(2, n=64)
-    w.nx, w.ny = 131, 70
-    w.rho = np.random.default_rng(4).uniform(2.5, 2.75, (2, 70, 131))
+    w.nx, w.ny = 512, 70
+    w.rho = np.random.default_rng(4).uniform(2.5, 2.75, (2, 70, 512))
     outs = []
     assert gpu_run(gpu, w, 0).schedule_count() == N_SCHED
     for s in range(N_SCHED):
