@@ -104,16 +104,16 @@ def copy_gbs(nbytes=1 << 30, reps=20):
 
 def traffic_from_profiles(kernel_key: str):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
-    recorded in profiles/traffic.md together with the hash of the sweep
+    recorded in profiles/ together with the hash of the sweep
     source they were taken on; None when the source has changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic.md")
+    path = os.path.join(ROOT, "profiles", "k_sweep_spinodal2048_f64_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     if not m or m.group(1) != sweep_source_hash():
         return None
-    m = re.search(rf"{re.escape(kernel_key)}\s*\|\s*([0-9.eE+]+)\s*\|", txt)
+    m = re.search(rf"traffic_bytes_per_launch:\s*{re.escape(kernel_key)}\s*=\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
 
@@ -124,6 +124,136 @@ def sweep_source_hash():
     for fn in ("sweep.hpp", "launch.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1805_07251_amd", "csrc", fn), "rb").read())
     return h.hexdigest()
+
+
+def batch_leg(seed, steps, warmup):
+    """The batched phase-diagram workload: 1024 quasi-1-D lattices L x 4,
+    L in [128, 1024], own kT / composition / a12, one persistent launch."""
+    import numpy as np
+    import torch
+
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd import vdwlb as V
+    from paper_1805_07251_amd.batch import Batch
+    from paper_1805_07251_amd.lattice import Lattice
+
+    def maxwell(a, b, kT):
+        try:
+            return V.maxwell(a, b, kT)
+        except V.VdwlbError:
+            return None
+
+    ws = I.batch_slabs(maxwell, seed)
+    sites = np.array([w.nx * w.ny for w in ws], dtype=np.float64)
+    C = ws[0].C
+    b = Batch(ws)
+    # launch shape: short timed runs of each candidate
+    best = None
+    for threads, blocks in ((1024, 0), (256, 0), (256, 512)):
+        b.set_launch(threads, blocks)
+        b.init([w.rho for w in ws])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.run(200)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        if best is None or t < best[0]:
+            best = (t, threads, blocks)
+    b.set_launch(best[1], best[2])
+    b.init([w.rho for w in ws])
+    b.run(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    st = b.status()
+    done = np.where(st == 0, steps, np.maximum(st - warmup, 0))
+    mlups_c = float((sites * done).sum() * C / secs / 1e6)
+    # the plain per-instance path on a subset spanning the size range
+    order = np.argsort(sites)
+    subset = [int(order[i]) for i in np.linspace(0, len(ws) - 1, 16).astype(int)]
+    nplain = 200
+    lats = []
+    for k in subset:
+        lat = Lattice.from_workload(ws[k])
+        lat.init(ws[k].rho)
+        lat.run(2)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.run(nplain)
+    torch.cuda.synchronize()
+    psecs = time.perf_counter() - t0
+    plain_mlups_c = float(sites[subset].sum() * nplain * C / psecs / 1e6)
+    return {
+        "workload": f"{len(ws)} lattices Lx4, L in [128,1024], C={C}, FP64, slab init",
+        "steps": steps,
+        "seconds": secs,
+        "launch": {"threads": best[1], "blocks": best[2]},
+        "mlups_x_c": mlups_c,
+        "instances_stopped_unphysical": int((st != 0).sum()),
+        "plain_per_instance_mlups_x_c": plain_mlups_c,
+        "plain_sample": f"16 instances across the size range, {nplain} steps each, one plan per instance",
+        "speedup_vs_plain_per_instance": mlups_c / plain_mlups_c,
+        "equivalent_streamed_gbs": mlups_c / C * 1e6 * 288 / 1e9,
+    }
+
+
+def adjoint_leg(seed):
+    """Gradient of a density-profile loss after 2000 steps of the 256 x 256
+    lattice w.r.t. (kT, a11, a12, a22, b1, b2, kappa), checkpoints every 100."""
+    import numpy as np
+    import torch
+
+    from paper_1805_07251_amd import adjoint as A
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd.lattice import Lattice
+
+    w, tgt = I.adjoint_case(seed)
+    theta = A.theta_from_params(w.kT, w.a, w.b, I.KAPPA)
+    spec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
+    rho0 = torch.as_tensor(w.rho, device="cuda")
+    tg = torch.as_tensor(tgt, device="cuda")
+    # warm-up (plans, graphs, allocator)
+    A.run_and_grad(theta, rho0, spec, lambda r: ((r[0] - tg) ** 2).sum())
+    torch.cuda.synchronize()
+    t = torch.as_tensor(theta).clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    rho = A.VdwLBFunction.apply(t, rho0, spec)
+    loss = ((rho[0] - tg) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # the plain forward for the same 2000 steps
+    lat = Lattice.from_workload(w)
+    lat.init(w.rho)
+    lat.run(10)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    lat.init(w.rho)
+    lat.run(2000)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    sites = w.nx * w.ny
+    return {
+        "workload": "256x256 D2Q9, C=2, FP64, 2000 steps, checkpoints every 100",
+        "forward_ms": (t1 - t0) * 1e3,
+        "backward_ms": (t2 - t1) * 1e3,
+        "plain_forward_ms": (t4 - t3) * 1e3,
+        "fwd_plus_bwd_over_plain_forward": ((t2 - t0) / (t4 - t3)),
+        "adjoint_mlups": sites * 2000 / (t2 - t1) / 1e6,
+        "loss": float(loss.detach().cpu()),
+        "grad": [float(v) for v in t.grad.cpu().numpy()],
+        "theta_names": ["kT", "a11", "a12", "a22", "b1", "b2", "kappa"],
+    }
 
 
 def cpu_baseline(w, steps=5):
@@ -163,7 +293,7 @@ def main():
         return
     sites = w.nx * w.ny
     achieved = head["gbs"]
-    traffic = traffic_from_profiles("k_sweep<double, 2")
+    traffic = traffic_from_profiles("k_sweep<double, 2>")
     out = {
         "metric": METRIC,
         "value": head["mlups_x_c"],
@@ -193,6 +323,8 @@ def main():
         w2 = I.mixture4(args.seed)
         extra["mixture4_1024_f32"] = sweep_line(w2, "f32", 5000, args.warmup)
         extra["copy_kernel_gbs"] = copy_gbs()
+        extra["batched"] = batch_leg(args.seed, 20000, 10)
+        extra["adjoint"] = adjoint_leg(args.seed)
     out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -200,3 +200,24 @@ def test_adjoint_case_against_finite_differences(gpu):
         ld = float(loss_fn(adjoint.VdwLBFunction.apply(torch.as_tensor(dn), rho0, spec)))
         fd = (lu - ld) / (2 * hh)
         assert abs(fd - grad[k]) <= 1e-4 * abs(grad[k]) + 1e-6 * np.abs(grad).max(), (k, fd, grad[k])
+
+
+def test_adjoint_case_against_oracle_complex_step(gpu):
+    """The same 256 x 256, 2000-step gradient against the complex-step
+    gradient of the CPU oracle stored in tests/golden/adjoint_256_2000.json
+    (written by tests/golden/make_adjoint_golden.py, oracle only)."""
+    import json
+    import os
+
+    adjoint, _, _ = gpu
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_256_2000.json")))
+    w, tgt = I.adjoint_case(0)
+    theta = adjoint.theta_from_params(w.kT, w.a, w.b, I.KAPPA)
+    np.testing.assert_allclose(theta, ref["theta"], rtol=1e-15)
+    spec = adjoint.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
+    tg = torch.as_tensor(tgt, device="cuda")
+    loss, grad = adjoint.run_and_grad(theta, torch.as_tensor(w.rho, device="cuda"), spec,
+                                      lambda r: ((r[0] - tg) ** 2).sum())
+    assert loss == pytest.approx(ref["loss"], rel=1e-11)
+    g = np.array(ref["grad"])
+    np.testing.assert_allclose(grad, g, rtol=1e-9, atol=1e-10 * np.abs(g).max())
