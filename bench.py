@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: the headline sweep for --steps steps and the 1 GiB copy kernel only")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="with --profile: use this sweep schedule instead of autotuning")
     return ap.parse_args()
 
 
@@ -54,12 +56,16 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3
 
 
-def sweep_line(w, dtype, steps, warmup):
+def sweep_line(w, dtype, steps, warmup, schedule=-1):
     from paper_1805_07251_amd.lattice import Lattice
 
     lat = Lattice.from_workload(w, dtype=dtype)
     lat.init(w.rho)
-    sched = lat.autotune()
+    if schedule >= 0:
+        lat.set_schedule(schedule)
+        sched = schedule
+    else:
+        sched = lat.autotune()
     lat.init(w.rho)
     secs = time_steps(lat, steps, warmup)
     st = lat.status()
@@ -286,7 +292,7 @@ def main():
 
     torch.cuda.set_device(0)
     w = I.spinodal_large(args.seed)
-    head = sweep_line(w, "f64", args.steps, args.warmup)
+    head = sweep_line(w, "f64", args.steps, args.warmup, args.schedule if args.profile else -1)
     if args.profile:
         gbs = copy_gbs(reps=5)
         print(json.dumps({"profile": True, "sweep": head, "copy_kernel_gbs": gbs, "copy_bytes": 1 << 30}))

@@ -61,7 +61,8 @@ enum { VDWLB_FORCE_LOG = 0, VDWLB_FORCE_NID = 1 }; /* Eq. forceMuLog / Eq. force
 
 /* Description of one lattice and its parameters (Secs. II, III, V).
  *   dim      2 (D2Q9).  1 (D1Q3) is reserved and returns VDWLB_E_UNSUPPORTED.
- *   nx, ny   periodic extents, >= 1 each (small extents wrap several times).
+ *   nx, ny   periodic extents, >= 1 each (small extents wrap several times),
+ *            nx * ny <= 2^28.
  *   ncomp    number of components C, 1 .. VDWLB_MAX_COMPONENTS.
  *   dtype    VDWLB_F64 or VDWLB_F32.
  *   force    VDWLB_FORCE_LOG (default of the paper's production runs) or NID.

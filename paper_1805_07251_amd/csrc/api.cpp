@@ -44,7 +44,7 @@ int32_t validate_desc(const vdwlb_desc* d) {
     if (!d) return VDWLB_E_INVALID_ARG;
     const int C = d->ncomp;
     if (d->nx < 1 || d->ny < 1 || C < 1) return VDWLB_E_INVALID_ARG;
-    if ((int64_t)d->nx * d->ny > (int64_t)1 << 30) return VDWLB_E_INVALID_ARG;
+    if ((int64_t)d->nx * d->ny > (int64_t)1 << 28) return VDWLB_E_INVALID_ARG;
     if (d->dim != 1 && d->dim != 2) return VDWLB_E_INVALID_ARG;
     if (d->dtype != VDWLB_F64 && d->dtype != VDWLB_F32) return VDWLB_E_INVALID_ARG;
     if (d->force != VDWLB_FORCE_LOG && d->force != VDWLB_FORCE_NID) return VDWLB_E_INVALID_ARG;
@@ -194,14 +194,13 @@ vdwlb_status vdwlb_moments(vdwlb_plan* p, const void* f, void* rho, void* mom, v
     return vdwlb_sync_status(p, stream);
 }
 
-int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? 2 * schedule_count() : 0; }
+int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? public_schedule_count() : 0; }
 
 vdwlb_status vdwlb_set_schedule(vdwlb_plan* p, int32_t k) {
-    if (!p || k < 0 || k >= 2 * schedule_count()) return VDWLB_E_INVALID_ARG;
-    const int sched = k % schedule_count(), mode = k / schedule_count();
-    if (sched != p->sched || mode != p->map_mode) release_graph(*p);
-    p->sched = sched;
-    p->map_mode = mode;
+    if (!p) return VDWLB_E_INVALID_ARG;
+    const int old_s = p->sched, old_m = p->map_mode;
+    if (!apply_public_schedule(*p, k)) return VDWLB_E_INVALID_ARG;
+    if (old_s != p->sched || old_m != p->map_mode) release_graph(*p);
     return VDWLB_OK;
 }
 
@@ -214,11 +213,10 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     const int64_t sites = (int64_t)p->nx * p->ny;
     const int reps = sites >= (1 << 20) ? 10 : 50;
     float best = 1e30f;
-    int best_k = p->sched, best_m = p->map_mode;
-    for (int km = 0; km < 2 * schedule_count(); ++km) {
-        const int k = km >> 1;
-        p->sched = k;
-        p->map_mode = km & 1;
+    const int keep_s = p->sched, keep_m = p->map_mode;
+    int best_k = -1;
+    for (int k = 0; k < public_schedule_count(); ++k) {
+        if (!apply_public_schedule(*p, k)) continue;  // not available for this lattice
         hipError_t e = hipSuccess;
         for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch_sweep(*p, fA, fB, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
@@ -230,20 +228,22 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
         if (e != hipSuccess) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
+            p->sched = keep_s;
+            p->map_mode = keep_m;
             return dev_fail(e, "autotune");
         }
         if (ms < best) {
             best = ms;
             best_k = k;
-            best_m = p->map_mode;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_graph(*p);
-    p->sched = best_k;
-    p->map_mode = best_m;
-    if (chosen) *chosen = best_k + best_m * schedule_count();
+    p->sched = keep_s;
+    p->map_mode = keep_m;
+    if (best_k >= 0) apply_public_schedule(*p, best_k);
+    if (chosen) *chosen = best_k;
     return VDWLB_OK;
 }
 

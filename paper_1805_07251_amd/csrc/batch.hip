@@ -55,13 +55,18 @@ __global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict
         g.wrap_general = g.nx < TX + 8 ? 1 : 0;
         T* A = poolA + I.offset;
         T* B = poolB + I.offset;
+        const bool tau1 = I.k.omega == 1.0;
         int fail = 0;
         for (int t = 0; t < nsteps; ++t) {
             const T* src = (t & 1) ? B : A;
             T* dst = (t & 1) ? A : B;
             bool bad = false;
             for (int x0 = 0; x0 < g.nx; x0 += TX) {
-                bad |= strip_step<T, C, TX, NY, false>(src, dst, g, I.k, x0, s_rho, s_phi);
+                // same collision form as the plain sweep of this instance (tau = 1 or not)
+                if (tau1)
+                    bad |= strip_step<T, C, TX, NY, false, true>(src, dst, g, I.k, x0, s_rho, s_phi);
+                else
+                    bad |= strip_step<T, C, TX, NY, false, false>(src, dst, g, I.k, x0, s_rho, s_phi);
                 __syncthreads();  // LDS reuse by the next strip; orders this step's stores before the next step
             }
             if (bad) s_bad = 1;
@@ -87,7 +92,8 @@ __global__ void k_batch_init(const Instance<C>* __restrict__ inst, T* __restrict
             T p[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) p[i] = T(0);
-            collide<T>(p, rho[I.rho_offset + (int64_t)c * n + s], T(0), T(0), T(0), T(0), T(0), T(1), T(0), T(0));
+            const T r = rho[I.rho_offset + (int64_t)c * n + s];
+            collide<T>(p, r, T(1) / r, T(0), T(0), T(0), T(0), T(0), T(1), T(0), T(0));
 #pragma unroll
             for (int i = 0; i < Q; ++i) pool[I.offset + (int64_t)(c * Q + i) * I.g.plane + s] = p[i];
         }

@@ -15,7 +15,7 @@ struct vdwlb_plan {
     int64_t plane = 0;
     int device = 0;
     int* d_flag = nullptr;  // sticky unphysical-state flag (device)
-    int sched = 0;          // index into the schedule table
+    int sched = 0;          // tile schedule index, or N_SCHEDULES + march index
     int map_mode = 0;       // workgroup -> tile order: 0 row-major ranges, 1 vertical XCD bands
     // captured step sequence, bound to one (fA, fB) pair and schedule
     hipGraphExec_t graph = nullptr;
@@ -38,6 +38,10 @@ struct Schedule {
 
 int schedule_count();
 Schedule schedule_at(int k);
+// Public schedule numbering: tile schedules in row-major XCD order, the same
+// in vertical-band order, then the march schedules.
+int public_schedule_count();
+bool apply_public_schedule(vdwlb_plan& p, int k);
 int default_schedule(const vdwlb_plan& p);
 bool graphs_enabled();
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "march.hpp"
 #include "sweep.hpp"
 
 namespace vdwlb {
@@ -19,10 +20,10 @@ namespace vdwlb {
     X(7, 32, 16, true, 0)      \
     X(8, 32, 32, true, 0)      \
     X(9, 128, 4, true, 0)      \
-    X(10, 64, 8, true, 5)      \
-    X(11, 32, 16, true, 5)     \
-    X(12, 32, 16, true, 6)     \
-    X(13, 64, 8, true, 6)
+    X(10, 32, 8, true, 0)      \
+    X(11, 64, 4, true, 0)      \
+    X(12, 16, 16, true, 0)     \
+    X(13, 32, 16, true, 6)
 
 #define VDWLB_SCHED_ENTRY(i, tx, ty, nt, occ) {tx, ty, nt, occ},
 constexpr Schedule SCHEDULES[] = {VDWLB_SCHEDULES(VDWLB_SCHED_ENTRY)};
@@ -58,6 +59,7 @@ Coeffs<C> make_coeffs(const vdwlb_plan& p) {
             k.lam[c][d] = p.lam[c * C + d];
         }
     }
+    k.fk = C >= 2 ? 1.0 / (1.0 + 0.5 * p.lam[1]) : 0.0;
     k.force = p.force;
     return k;
 }
@@ -67,8 +69,12 @@ hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream
     const Geometry g = make_geometry(p, TX, TY);
     const Coeffs<C> k = make_coeffs<C>(p);
     const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin, (T*)fout, g, k,
-                       p.d_flag);
+    if (p.tau == 1.0)
+        hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, true>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
+                           (T*)fout, g, k, p.d_flag);
+    else
+        hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, false>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
+                           (T*)fout, g, k, p.d_flag);
     return hipGetLastError();
 }
 
@@ -83,13 +89,62 @@ hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hip
     }
 }
 
+// March schedules (wavefronts per workgroup, keep populations in registers,
+// rows per chunk); they follow the tile schedules in the schedule numbering.
+#define VDWLB_MARCH(X)    \
+    X(0, 4, false, 32)    \
+    X(1, 4, false, 64)    \
+    X(2, 4, false, 128)   \
+    X(3, 4, true, 32)     \
+    X(4, 4, true, 64)     \
+    X(5, 4, true, 128)
+constexpr int N_MARCH = 6;
+
+inline bool march_supported(const vdwlb_plan& p) { return p.nx >= 64 && p.ny >= 8; }
+
+template <typename T, int C, int NW, bool KEEP>
+hipError_t run_march(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, int h) {
+    Geometry g = make_geometry(p, 64, 8);
+    g.wrap_general = (p.nx < 72 || p.ny < 8) ? 1 : 0;
+    MarchGeometry mg;
+    mg.n_strips = (p.nx + MARCH_W - 1) / MARCH_W;
+    mg.h = h;
+    mg.n_chunks = (p.ny + h - 1) / h;
+    const int items = mg.n_strips * mg.n_chunks;
+    const int wgs = (items + NW - 1) / NW;
+    if (p.tau == 1.0)
+        hipLaunchKernelGGL((k_march<T, C, NW, KEEP, true>), dim3(wgs), dim3(64 * NW), 0, s, (const T*)fin, (T*)fout,
+                           g, mg, make_coeffs<C>(p), p.d_flag);
+    else
+        hipLaunchKernelGGL((k_march<T, C, NW, KEEP, false>), dim3(wgs), dim3(64 * NW), 0, s, (const T*)fin,
+                           (T*)fout, g, mg, make_coeffs<C>(p), p.d_flag);
+    return hipGetLastError();
+}
+
+template <typename T, int C>
+hipError_t run_march_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, int m) {
+    switch (m) {
+#define VDWLB_MARCH_CASE(i, nw, keep, h) \
+    case i: return run_march<T, C, nw, keep>(p, fin, fout, s, h);
+        VDWLB_MARCH(VDWLB_MARCH_CASE)
+#undef VDWLB_MARCH_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int C>
+hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    if (p.sched >= N_SCHEDULES) return run_march_sched<T, C>(p, fin, fout, s, p.sched - N_SCHEDULES);
+    return run_sweep_sched<T, C>(p, fin, fout, s);
+}
+
 template <typename T>
 hipError_t run_sweep_typed(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
     switch (p.C) {
-        case 1: return run_sweep_sched<T, 1>(p, fin, fout, s);
-        case 2: return run_sweep_sched<T, 2>(p, fin, fout, s);
-        case 3: return run_sweep_sched<T, 3>(p, fin, fout, s);
-        case 4: return run_sweep_sched<T, 4>(p, fin, fout, s);
+        case 1: return run_any<T, 1>(p, fin, fout, s);
+        case 2: return run_any<T, 2>(p, fin, fout, s);
+        case 3: return run_any<T, 3>(p, fin, fout, s);
+        case 4: return run_any<T, 4>(p, fin, fout, s);
         default: return hipErrorInvalidValue;
     }
 }

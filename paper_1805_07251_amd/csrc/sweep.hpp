@@ -49,6 +49,7 @@ struct Coeffs {
     double kap[C][C];
     double lam[C][C];
     double b[C];
+    double fk;  // 1 / (1 + lambda^{01}/2): closed-form friction factor for C = 2
     int force;  // 0 log, 1 nid
 };
 
@@ -97,12 +98,24 @@ __device__ __forceinline__ void pull_offsets(const Geometry& g, int x, int y, in
     o[8] = rp + xm;
 }
 
+// Element idx of a plane: a workgroup-uniform base pointer plus a 32-bit byte
+// offset (plans keep a plane below 2^28 elements), so the loads and stores
+// use a scalar base with a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, int idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* base, int idx) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
+}
+
 template <typename T, int C>
 __device__ __forceinline__ void pull(const T* __restrict__ f, const Geometry& g, const int (&o)[Q], T (&p)[C][Q]) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int i = 0; i < Q; ++i) p[c][i] = f[(int64_t)(c * Q + i) * g.plane + o[i]];
+        for (int i = 0; i < Q; ++i) p[c][i] = at(f + (int64_t)(c * Q + i) * g.plane, o[i]);
 }
 
 // rho = sum_i f_i, summed in velocity order.
@@ -179,14 +192,14 @@ __device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], 
 // uh = u + G/(2 rho), G including the friction): solve
 // rho^c uh^c - 1/2 sum_c' W^{cc'} (uh^c' - uh^c) = j^c + G_mu^c / 2,
 // W^{cc'} = lambda^{cc'} rho^c rho^c'/(rho^c + rho^c'), then
-// G_f^c = sum_c' W^{cc'} (uh^c' - uh^c), added to g in place.
+// G_f^c = sum_c' W^{cc'} (uh^c' - uh^c), added to g in place.  ri = 1/rho.
 template <typename T, int C>
-__device__ __forceinline__ void friction(const T (&rho)[C], const T (&j)[C], T (&g)[C], const T (&W)[C][C]) {
+__device__ __forceinline__ void friction(const T (&rho)[C], const T (&ri)[C], const T (&j)[C], T (&g)[C],
+                                         const T (&W)[C][C], T fk) {
     if constexpr (C == 2) {
-        // closed form: the velocity difference shrinks by 1 + lambda/2
-        const T d0 = (j[1] + T(0.5) * g[1]) / rho[1] - (j[0] + T(0.5) * g[0]) / rho[0];
-        const T lam = W[0][1] * (rho[0] + rho[1]) / (rho[0] * rho[1]);
-        const T gf = W[0][1] * d0 / (T(1) + T(0.5) * lam);
+        // closed form: the velocity difference shrinks by fk = 1/(1 + lambda/2)
+        const T d0 = (j[1] + T(0.5) * g[1]) * ri[1] - (j[0] + T(0.5) * g[0]) * ri[0];
+        const T gf = W[0][1] * fk * d0;
         g[0] += gf;
         g[1] -= gf;
     } else if constexpr (C > 2) {
@@ -230,13 +243,18 @@ __device__ __forceinline__ void friction(const T (&rho)[C], const T (&j)[C], T (
             g[c] += gf;
         }
     }
+    (void)ri;
+    (void)fk;
 }
 
 // Forced BGK collision of one component at one site: returns the 9
 // post-collision populations in p (in place).
-template <typename T>
-__device__ __forceinline__ void collide(T (&p)[Q], T rho, T jx, T jy, T gx, T gy, T lap, T omega, T cG, T cL) {
-    const T ri = T(1) / rho;
+// TAU1 (tau = 1): f' = feq + F, which does not read the pulled populations,
+// so kernels can drop them after the moments.  Opposite velocities share the
+// even parts (in v) of feq and F and negate the odd parts, so each pair
+// (1,3), (2,4), (5,7), (6,8) is evaluated once.
+template <typename T, bool TAU1 = false>
+__device__ __forceinline__ void collide(T (&p)[Q], T rho, T ri, T jx, T jy, T gx, T gy, T lap, T omega, T cG, T cL) {
     const T ux = jx * ri, uy = jy * ri;
     const T sxx = T(2) * gx * ux + cG * gx * gx * ri + cL * lap;
     const T syy = T(2) * gy * uy + cG * gy * gy * ri + cL * lap;
@@ -244,16 +262,42 @@ __device__ __forceinline__ void collide(T (&p)[Q], T rho, T jx, T jy, T gx, T gy
     const T uu = ux * ux + uy * uy;
     const T base = T(1) - T(1.5) * uu;
     const T ftr = -T(1.5) * (sxx + syy);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        constexpr T W0 = T(4.0 / 9.0), W1 = T(1.0 / 9.0), W2 = T(1.0 / 36.0);
-        const T w = i == 0 ? W0 : (i < 5 ? W1 : W2);
-        const int vx = VX[i], vy = VY[i];
-        const T vu = T(vx) * ux + T(vy) * uy;
-        const T feq = w * rho * (base + vu * (T(3) + T(4.5) * vu));
-        const T svv = T(vx * vx) * sxx + T(vy * vy) * syy + T(2 * vx * vy) * sxy;
-        const T force = w * (T(3) * (T(vx) * gx + T(vy) * gy) + T(4.5) * svv + ftr);
-        p[i] = p[i] + omega * (feq - p[i]) + force;
+    constexpr T W0 = T(4.0 / 9.0), W1 = T(1.0 / 9.0), W2 = T(1.0 / 36.0);
+    const T r1 = W1 * rho, r2 = W2 * rho;
+    // new population from feq = even + odd and force = fe + fo
+    auto out = [&](int i, T feq, T force) {
+        if constexpr (TAU1) p[i] = feq + force;
+        else p[i] = p[i] + omega * (feq - p[i]) + force;
+    };
+    out(0, W0 * rho * base, W0 * ftr);
+    // axis pairs: v = +-(1,0), +-(0,1)
+    {
+        const T ev = r1 * (base + T(4.5) * ux * ux), od = T(3) * r1 * ux;
+        const T fe = W1 * (T(4.5) * sxx + ftr), fo = T(3) * W1 * gx;
+        out(1, ev + od, fe + fo);
+        out(3, ev - od, fe - fo);
+    }
+    {
+        const T ev = r1 * (base + T(4.5) * uy * uy), od = T(3) * r1 * uy;
+        const T fe = W1 * (T(4.5) * syy + ftr), fo = T(3) * W1 * gy;
+        out(2, ev + od, fe + fo);
+        out(4, ev - od, fe - fo);
+    }
+    // diagonal pairs: v = +-(1,1), +-(-1,1)
+    const T sd = sxx + syy;
+    {
+        const T vu = ux + uy;
+        const T ev = r2 * (base + T(4.5) * vu * vu), od = T(3) * r2 * vu;
+        const T fe = W2 * (T(4.5) * (sd + T(2) * sxy) + ftr), fo = T(3) * W2 * (gx + gy);
+        out(5, ev + od, fe + fo);
+        out(7, ev - od, fe - fo);
+    }
+    {
+        const T vu = uy - ux;
+        const T ev = r2 * (base + T(4.5) * vu * vu), od = T(3) * r2 * vu;
+        const T fe = W2 * (T(4.5) * (sd - T(2) * sxy) + ftr), fo = T(3) * W2 * (gy - gx);
+        out(6, ev + od, fe + fo);
+        out(8, ev - od, fe - fo);
     }
 }
 
@@ -287,35 +331,42 @@ __device__ __forceinline__ void pull_density(const T* __restrict__ f, const Geom
     for (int c = 0; c < C; ++c) {
         T q[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) q[i] = f[(int64_t)(c * Q + i) * g.plane + o[i]];
+        for (int i = 0; i < Q; ++i) q[i] = at(f + (int64_t)(c * Q + i) * g.plane, o[i]);
         dst[c * stride] = density<T>(q);
     }
 }
 
 // Friction, collision and store of one site whose pulled populations p,
 // density, momentum, mean-field force g and density Laplacian are known.
-template <typename T, int C, bool NTSTORE>
+template <typename T, int C, bool NTSTORE, bool TAU1>
 __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T (&jx)[C], T (&jy)[C], T (&gx)[C],
                                               T (&gy)[C], const T (&lap)[C], const Coeffs<C>& k,
                                               T* __restrict__ fout, int64_t plane, int s) {
+    T ri[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ri[c] = T(1) / rho[c];
     if constexpr (C > 1) {
+        // W = lambda rho rho' / (rho + rho') = lambda / (1/rho + 1/rho')
         T W[C][C];
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = 0; d < C; ++d)
-                W[c][d] = c == d ? T(0) : T(k.lam[c][d]) * rho[c] * rho[d] / (rho[c] + rho[d]);
-        friction<T, C>(rho, jx, gx, W);
-        friction<T, C>(rho, jy, gy, W);
+            for (int d = 0; d < C; ++d) W[c][d] = T(0);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) / (ri[c] + ri[d]);
+        friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
+        friction<T, C>(rho, ri, jy, gy, W, T(k.fk));
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        collide<T>(p[c], rho[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
+        collide<T, TAU1>(p[c], rho[c], ri[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            T* dst = fout + (int64_t)(c * Q + i) * plane + s;
-            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], dst);
-            else *dst = p[c][i];
+            T& dst = at(fout + (int64_t)(c * Q + i) * plane, s);
+            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], &dst);
+            else dst = p[c][i];
         }
     }
 }
@@ -343,7 +394,7 @@ __device__ __forceinline__ void put_wrapped(T* plane, int row, int e, T v) {
 // only the x ring is recomputed.  Executed by TX * NY threads.  Every site
 // goes through the same arithmetic as in the plain sweep (same functions and
 // stencil expressions), so results are bit-identical to it.
-template <typename T, int C, int TX, int NY, bool NTSTORE>
+template <typename T, int C, int TX, int NY, bool NTSTORE, bool TAU1>
 __device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restrict__ fout, const Geometry& g,
                                            const Coeffs<C>& k, int x0, T* s_rho, T* s_phi) {
     using L = StripLds<TX, NY>;
@@ -403,21 +454,21 @@ __device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restr
                 gy[c] += T(THETA) * ry;
             }
         }
-        collide_store<T, C, NTSTORE>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, ly * g.nx + x);
+        collide_store<T, C, NTSTORE, TAU1>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, ly * g.nx + x);
     }
     return bad;
 }
 
 // The plain sweep: one launch per time step, one workgroup per TX x TY tile.
 // Phase 1 pulls the 9C populations of each interior site into registers
-// (reused by the collision) and the densities of the radius-2 ring around the
+// (reused by the collision unless tau = 1) and the densities of the radius-2 ring around the
 // tile (re-read from L2/MALL, never stored) into LDS; phase 2 evaluates the
 // potential on the tile plus a radius-1 ring; phase 3 takes gradients and the
 // Laplacian from LDS and collides.
 // NTSTORE: non-temporal stores of the new state, so that output lines do not
 // displace halo lines in L2.  OCC > 0 asks the compiler for at least OCC waves
 // per SIMD (a VGPR budget of 512 / OCC).
-template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC>
+template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC, bool TAU1>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k, int* __restrict__ flag) {
     constexpr int NT = TX * TY, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
@@ -482,7 +533,7 @@ k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k
             gy[c] += T(THETA) * ry;
         }
     }
-    collide_store<T, C, NTSTORE>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, y * g.nx + x);
+    collide_store<T, C, NTSTORE, TAU1>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, y * g.nx + x);
 }
 
 // f_i^c = f^0_i(rho^c, u^c) (Eq. feq).
@@ -503,7 +554,7 @@ __global__ void k_init(T* __restrict__ f, const T* __restrict__ rho, const T* __
             jy = mom[(int64_t)(2 * c + 1) * n + s];
         }
         // collide with omega = 1 and no force from p = 0 gives exactly f^0
-        collide<T>(p, r, jx, jy, T(0), T(0), T(0), T(1), T(0), T(0));
+        collide<T>(p, r, T(1) / r, jx, jy, T(0), T(0), T(0), T(1), T(0), T(0));
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[(int64_t)(c * Q + i) * g.plane + s] = p[i];
     }
