@@ -14,10 +14,14 @@
  * second-moment correction of Eq. forceCorrectionsPsi).
  *
  * Conventions fixed by this interface
- *  - Populations are stored structure-of-arrays: f[c][i][s] with plane stride
- *    vdwlb_plane_elems() elements and site s = y*nx + x (x fastest).  The
- *    velocity order is v_0 = (0,0), v_1..4 = (1,0),(0,1),(-1,0),(0,-1),
- *    v_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
+ *  - Populations are stored as nine velocity planes of sites with the C
+ *    components of a site adjacent: f_i^c at site s = y*nx + x (x fastest) is
+ *    element (i * P + s) * C + c, P = vdwlb_plane_elems() sites per plane.
+ *    One site's populations of all components are then a single vector
+ *    access.  Population buffers must be aligned to C * sizeof(dtype) bytes
+ *    (hipMalloc memory always is); misaligned pointers return
+ *    VDWLB_E_INVALID_ARG.  The velocity order is v_0 = (0,0),
+ *    v_1..4 = (1,0),(0,1),(-1,0),(0,-1), v_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
  *  - A stored state is post-collision, pre-stream; a step reads f_i(x - v_i)
  *    from one buffer and writes the new state to the other (ping-pong).
  *  - Physical force convention: momentum of component c gains
@@ -62,7 +66,8 @@ enum { VDWLB_FORCE_LOG = 0, VDWLB_FORCE_NID = 1 }; /* Eq. forceMuLog / Eq. force
 /* Description of one lattice and its parameters (Secs. II, III, V).
  *   dim      2 (D2Q9).  1 (D1Q3) is reserved and returns VDWLB_E_UNSUPPORTED.
  *   nx, ny   periodic extents, >= 1 each (small extents wrap several times),
- *            nx * ny <= 2^28.
+ *            nx * ny <= 2^28 and one plane of a population buffer below
+ *            2^32 bytes (plane_elems * C * sizeof(dtype)).
  *   ncomp    number of components C, 1 .. VDWLB_MAX_COMPONENTS.
  *   dtype    VDWLB_F64 or VDWLB_F32.
  *   force    VDWLB_FORCE_LOG (default of the paper's production runs) or NID.
@@ -111,8 +116,8 @@ vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out);
 /* Release the plan, its device flag word and its cached graphs (NULL is a no-op). */
 vdwlb_status vdwlb_plan_destroy(vdwlb_plan* plan);
 
-/* Elements between consecutive (c, i) planes of a population buffer
- * (nx*ny rounded up to a multiple of 64). */
+/* Sites per velocity plane of a population buffer (nx*ny rounded up to a
+ * multiple of 64); a plane holds plane_elems * C elements. */
 int64_t vdwlb_plane_elems(const vdwlb_plan* plan);
 
 /* Bytes of one population buffer: 9 * C * plane_elems * sizeof(dtype).
@@ -262,8 +267,9 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* plan, const void* rho_bar, const 
  * segment, is replaced by the cotangent of f_ckpt, and the parameter
  * cotangents of the segment are added to pbar_accum (device, see above).
  * workspace: vdwlb_adjoint_workspace_bytes(plan, nsteps) bytes of device
- * memory owned by the caller.  The summation order is fixed, so results are
- * deterministic.  Asynchronous on stream. */
+ * memory owned by the caller, aligned like a population buffer.  The
+ * summation order is fixed, so results are deterministic.  Asynchronous on
+ * stream. */
 vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
                                    void* workspace, double* pbar_accum, void* stream);
 

@@ -88,5 +88,5 @@ class Batch:
         """Populations of instance k as [C, 9, ny, nx] (a copy)."""
         C, ny, nx = self.shapes[k]
         plane = (nx * ny + 63) // 64 * 64
-        v = self.pools[self.cur][self.offsets[k]:self.offsets[k] + 9 * C * plane].view(C, 9, plane)
-        return v[:, :, :nx * ny].reshape(C, 9, ny, nx).clone()
+        v = self.pools[self.cur][self.offsets[k]:self.offsets[k] + 9 * C * plane].view(9, plane, C)
+        return v[:, :nx * ny, :].permute(2, 0, 1).reshape(C, 9, ny, nx).clone()

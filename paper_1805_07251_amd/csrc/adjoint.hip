@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-            const double fb = w * fbn[(int64_t)(c * Q + i) * g.plane + s];
+            const double fb = w * fbn[((int64_t)i * g.plane + s) * C + c];
             const double vx = VX[i], vy = VY[i];
             M0 += fb;
             Mx += fb * vx;
@@ -334,10 +334,10 @@ __global__ void __launch_bounds__(BLK) k_adj_c(const double* __restrict__ fbn, d
         const double jbx = F.jb[(int64_t)(2 * c) * N + s], jby = F.jb[(int64_t)(2 * c + 1) * N + s];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double pb = (1.0 - omega) * fbn[(int64_t)(c * Q + i) * g.plane + s] + rb + jbx * VX[i] +
+            const double pb = (1.0 - omega) * fbn[((int64_t)i * g.plane + s) * C + c] + rb + jbx * VX[i] +
                               jby * VY[i];
             const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
-            fbo[(int64_t)(c * Q + i) * g.plane + t] = pb;
+            fbo[((int64_t)i * g.plane + t) * C + c] = pb;
         }
     }
 }
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(BLK) k_moments_adj(const double* __restrict__ 
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
-            fb[(int64_t)(c * Q + i) * g.plane + t] = rb + jbx * VX[i] + jby * VY[i];
+            fb[((int64_t)i * g.plane + t) * C + c] = rb + jbx * VX[i] + jby * VY[i];
         }
     }
 }
@@ -446,7 +446,7 @@ size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* p, int32_t nsteps) {
 
 vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const void* mom_bar, void* fbar,
                                    void* stream) {
-    if (!p || !fbar || (!rho_bar && !mom_bar)) return VDWLB_E_INVALID_ARG;
+    if (!p || !fbar || (!rho_bar && !mom_bar) || !state_aligned(*p, fbar)) return VDWLB_E_INVALID_ARG;
     if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
     const Geometry g = make_geometry(*p, adj::TX, adj::TY);
     const int nb = (int)(((int64_t)p->nx * p->ny + adj::BLK - 1) / adj::BLK);
@@ -465,6 +465,8 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const voi
 vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io, void* workspace,
                                    double* pbar_accum, void* stream) {
     if (!p || !f_ckpt || !fbar_io || !workspace || !pbar_accum || nsteps < 1) return VDWLB_E_INVALID_ARG;
+    if (!state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io) || !state_aligned(*p, workspace))
+        return VDWLB_E_INVALID_ARG;
     if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const Layout L = layout(*p, nsteps);

@@ -47,6 +47,10 @@ int32_t validate_desc(const vdwlb_desc* d) {
     if ((int64_t)d->nx * d->ny > (int64_t)1 << 28) return VDWLB_E_INVALID_ARG;
     if (d->dim != 1 && d->dim != 2) return VDWLB_E_INVALID_ARG;
     if (d->dtype != VDWLB_F64 && d->dtype != VDWLB_F32) return VDWLB_E_INVALID_ARG;
+    if (C <= VDWLB_MAX_COMPONENTS) {  // kernels address a plane with 32-bit byte offsets
+        const int64_t plane = ((int64_t)d->nx * d->ny + 63) / 64 * 64;
+        if (plane * C * (d->dtype == VDWLB_F64 ? 8 : 4) > (int64_t)0xffffffff) return VDWLB_E_INVALID_ARG;
+    }
     if (d->force != VDWLB_FORCE_LOG && d->force != VDWLB_FORCE_NID) return VDWLB_E_INVALID_ARG;
     if (!(d->tau > 0.5) || !is_finite(d->tau)) return VDWLB_E_INVALID_ARG;
     if (!(d->kT > 0) || !is_finite(d->kT) || !is_finite(d->gamma_mu)) return VDWLB_E_INVALID_ARG;
@@ -149,13 +153,14 @@ size_t vdwlb_state_bytes(const vdwlb_plan* p) {
 }
 
 vdwlb_status vdwlb_init(vdwlb_plan* p, void* f, const void* rho, const void* mom, void* stream) {
-    if (!p || !f || !rho) return VDWLB_E_INVALID_ARG;
+    if (!p || !f || !rho || !state_aligned(*p, f)) return VDWLB_E_INVALID_ARG;
     hipError_t e = launch_init(*p, f, rho, mom, (hipStream_t)stream);
     return e == hipSuccess ? VDWLB_OK : dev_fail(e, "init kernel");
 }
 
 vdwlb_status vdwlb_step(vdwlb_plan* p, void* fA, void* fB, int64_t n, void* stream, int32_t* out_which) {
     if (!p || !fA || !fB || fA == fB || n < 0) return VDWLB_E_INVALID_ARG;
+    if (!state_aligned(*p, fA) || !state_aligned(*p, fB)) return VDWLB_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     int64_t done = 0;
     const int64_t per_graph = 2 * (int64_t)GRAPH_PAIRS;
@@ -188,7 +193,7 @@ vdwlb_status vdwlb_sync_status(vdwlb_plan* p, void* stream) {
 }
 
 vdwlb_status vdwlb_moments(vdwlb_plan* p, const void* f, void* rho, void* mom, void* mu, void* pr, void* stream) {
-    if (!p || !f || !rho) return VDWLB_E_INVALID_ARG;
+    if (!p || !f || !rho || !state_aligned(*p, f)) return VDWLB_E_INVALID_ARG;
     hipError_t e = launch_moments(*p, f, rho, mom, mu, pr, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "moments kernels");
     return vdwlb_sync_status(p, stream);
@@ -206,6 +211,7 @@ vdwlb_status vdwlb_set_schedule(vdwlb_plan* p, int32_t k) {
 
 vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* stream, int32_t* chosen) {
     if (!p || !fA || !fB || fA == fB) return VDWLB_E_INVALID_ARG;
+    if (!state_aligned(*p, fA) || !state_aligned(*p, fB)) return VDWLB_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));

@@ -86,17 +86,23 @@ template <typename T, int C>
 __global__ void k_batch_init(const Instance<C>* __restrict__ inst, T* __restrict__ pool, const T* __restrict__ rho) {
     const Instance<C>& I = inst[blockIdx.x];
     const int n = I.g.nx * I.g.ny;
-    for (int s = threadIdx.x; s < n; s += blockDim.x)
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        T p[C][Q];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            T p[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) p[i] = T(0);
+            for (int i = 0; i < Q; ++i) p[c][i] = T(0);
             const T r = rho[I.rho_offset + (int64_t)c * n + s];
-            collide<T>(p, r, T(1) / r, T(0), T(0), T(0), T(0), T(0), T(1), T(0), T(0));
-#pragma unroll
-            for (int i = 0; i < Q; ++i) pool[I.offset + (int64_t)(c * Q + i) * I.g.plane + s] = p[i];
+            collide<T>(p[c], r, T(1) / r, T(0), T(0), T(0), T(0), T(0), T(1), T(0), T(0));
         }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T v[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = p[c][i];
+            store_site<T, C, false>(plane_base<T, C>(pool + I.offset, i, I.g.plane), s, v);
+        }
+    }
 }
 
 // Densities of the streamed populations of every instance.
@@ -228,6 +234,10 @@ void fill_instances(vdwlb_batch& b, const std::vector<vdwlb_plan>& plans, std::v
     }
 }
 
+bool pool_aligned(const vdwlb_batch& b, const void* pool) {
+    return reinterpret_cast<uintptr_t>(pool) % state_alignment(b.C, b.dtype) == 0;
+}
+
 int device_blocks(const vdwlb_batch& b) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -347,13 +357,13 @@ vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* b, int32_t threads, int32_t blo
 }
 
 vdwlb_status vdwlb_batch_init(vdwlb_batch* b, void* pool, const void* rho, void* stream) {
-    if (!b || !pool || !rho) return VDWLB_E_INVALID_ARG;
+    if (!b || !pool || !rho || !pool_aligned(*b, pool)) return VDWLB_E_INVALID_ARG;
     hipError_t e = batch_aux(*b, 0, pool, const_cast<void*>(rho), (hipStream_t)stream);
     return e == hipSuccess ? VDWLB_OK : bfail(e, "batch init");
 }
 
 vdwlb_status vdwlb_batch_density(vdwlb_batch* b, const void* pool, void* rho, void* stream) {
-    if (!b || !pool || !rho) return VDWLB_E_INVALID_ARG;
+    if (!b || !pool || !rho || !pool_aligned(*b, pool)) return VDWLB_E_INVALID_ARG;
     hipError_t e = batch_aux(*b, 1, const_cast<void*>(pool), rho, (hipStream_t)stream);
     return e == hipSuccess ? VDWLB_OK : bfail(e, "batch density");
 }
@@ -361,6 +371,7 @@ vdwlb_status vdwlb_batch_density(vdwlb_batch* b, const void* pool, void* rho, vo
 vdwlb_status vdwlb_batch_run(vdwlb_batch* b, void* poolA, void* poolB, int64_t nsteps, void* stream,
                              int32_t* out_which) {
     if (!b || !poolA || !poolB || poolA == poolB || nsteps < 0 || nsteps > 0x7fffffff) return VDWLB_E_INVALID_ARG;
+    if (!pool_aligned(*b, poolA) || !pool_aligned(*b, poolB)) return VDWLB_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     int blocks = b->blocks > 0 ? b->blocks : device_blocks(*b);
     if (blocks > b->n) blocks = b->n;

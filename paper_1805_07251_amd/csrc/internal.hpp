@@ -15,7 +15,7 @@ struct vdwlb_plan {
     int64_t plane = 0;
     int device = 0;
     int* d_flag = nullptr;  // sticky unphysical-state flag (device)
-    int sched = 0;          // tile schedule index, or N_SCHEDULES + march index
+    int sched = 0;          // tile schedule index
     int map_mode = 0;       // workgroup -> tile order: 0 row-major ranges, 1 vertical XCD bands
     // captured step sequence, bound to one (fA, fB) pair and schedule
     hipGraphExec_t graph = nullptr;
@@ -38,9 +38,19 @@ struct Schedule {
 
 int schedule_count();
 Schedule schedule_at(int k);
-// Public schedule numbering: tile schedules in row-major XCD order, the same
-// in vertical-band order, then the march schedules.
+// Public schedule numbering: tile schedules in row-major XCD order, then the
+// same in vertical-band order.
 int public_schedule_count();
+
+// Alignment the kernels need for a population buffer: the C components of a
+// site are one vector access when C is 2 or 4.
+inline size_t state_alignment(int C, int dtype) {
+    const size_t e = dtype == VDWLB_F64 ? 8 : 4;
+    return (C == 2 || C == 4) ? C * e : e;
+}
+inline bool state_aligned(const vdwlb_plan& p, const void* f) {
+    return reinterpret_cast<uintptr_t>(f) % state_alignment(p.C, p.dtype) == 0;
+}
 bool apply_public_schedule(vdwlb_plan& p, int k);
 int default_schedule(const vdwlb_plan& p);
 bool graphs_enabled();

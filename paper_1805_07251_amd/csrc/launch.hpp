@@ -2,7 +2,6 @@
 #pragma once
 
 #include "internal.hpp"
-#include "march.hpp"
 #include "sweep.hpp"
 
 namespace vdwlb {
@@ -10,20 +9,20 @@ namespace vdwlb {
 // Tile schedules of the sweep (TX x TY sites per workgroup, non-temporal
 // stores, minimum waves per SIMD); the autotuner picks one per plan.
 #define VDWLB_SCHEDULES(X)     \
-    X(0, 64, 4, false, 0)      \
-    X(1, 64, 8, false, 0)      \
-    X(2, 32, 8, false, 0)      \
-    X(3, 64, 16, false, 0)     \
-    X(4, 128, 4, false, 0)     \
-    X(5, 32, 16, false, 0)     \
-    X(6, 64, 8, true, 0)       \
-    X(7, 32, 16, true, 0)      \
-    X(8, 32, 32, true, 0)      \
-    X(9, 128, 4, true, 0)      \
-    X(10, 32, 8, true, 0)      \
-    X(11, 64, 4, true, 0)      \
-    X(12, 16, 16, true, 0)     \
-    X(13, 32, 16, true, 6)
+    X(0, 64, 4, true, 0)       \
+    X(1, 64, 8, true, 0)       \
+    X(2, 32, 8, true, 0)       \
+    X(3, 64, 16, true, 0)      \
+    X(4, 128, 4, true, 0)      \
+    X(5, 32, 16, true, 0)      \
+    X(6, 32, 32, true, 0)      \
+    X(7, 128, 8, true, 0)      \
+    X(8, 64, 8, false, 0)      \
+    X(9, 32, 16, false, 0)     \
+    X(10, 64, 16, false, 0)    \
+    X(11, 16, 16, true, 0)     \
+    X(12, 64, 8, true, 8)      \
+    X(13, 64, 16, true, 8)
 
 #define VDWLB_SCHED_ENTRY(i, tx, ty, nt, occ) {tx, ty, nt, occ},
 constexpr Schedule SCHEDULES[] = {VDWLB_SCHEDULES(VDWLB_SCHED_ENTRY)};
@@ -89,52 +88,8 @@ hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hip
     }
 }
 
-// March schedules (wavefronts per workgroup, keep populations in registers,
-// rows per chunk); they follow the tile schedules in the schedule numbering.
-#define VDWLB_MARCH(X)    \
-    X(0, 4, false, 32)    \
-    X(1, 4, false, 64)    \
-    X(2, 4, false, 128)   \
-    X(3, 4, true, 32)     \
-    X(4, 4, true, 64)     \
-    X(5, 4, true, 128)
-constexpr int N_MARCH = 6;
-
-inline bool march_supported(const vdwlb_plan& p) { return p.nx >= 64 && p.ny >= 8; }
-
-template <typename T, int C, int NW, bool KEEP>
-hipError_t run_march(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, int h) {
-    Geometry g = make_geometry(p, 64, 8);
-    g.wrap_general = (p.nx < 72 || p.ny < 8) ? 1 : 0;
-    MarchGeometry mg;
-    mg.n_strips = (p.nx + MARCH_W - 1) / MARCH_W;
-    mg.h = h;
-    mg.n_chunks = (p.ny + h - 1) / h;
-    const int items = mg.n_strips * mg.n_chunks;
-    const int wgs = (items + NW - 1) / NW;
-    if (p.tau == 1.0)
-        hipLaunchKernelGGL((k_march<T, C, NW, KEEP, true>), dim3(wgs), dim3(64 * NW), 0, s, (const T*)fin, (T*)fout,
-                           g, mg, make_coeffs<C>(p), p.d_flag);
-    else
-        hipLaunchKernelGGL((k_march<T, C, NW, KEEP, false>), dim3(wgs), dim3(64 * NW), 0, s, (const T*)fin,
-                           (T*)fout, g, mg, make_coeffs<C>(p), p.d_flag);
-    return hipGetLastError();
-}
-
-template <typename T, int C>
-hipError_t run_march_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, int m) {
-    switch (m) {
-#define VDWLB_MARCH_CASE(i, nw, keep, h) \
-    case i: return run_march<T, C, nw, keep>(p, fin, fout, s, h);
-        VDWLB_MARCH(VDWLB_MARCH_CASE)
-#undef VDWLB_MARCH_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename T, int C>
 hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
-    if (p.sched >= N_SCHEDULES) return run_march_sched<T, C>(p, fin, fout, s, p.sched - N_SCHEDULES);
     return run_sweep_sched<T, C>(p, fin, fout, s);
 }
 

@@ -12,24 +12,18 @@ namespace vdwlb {
 int schedule_count() { return N_SCHEDULES; }
 Schedule schedule_at(int k) { return SCHEDULES[k]; }
 
-int public_schedule_count() { return 2 * N_SCHEDULES + N_MARCH; }
+int public_schedule_count() { return 2 * N_SCHEDULES; }
 
 bool apply_public_schedule(vdwlb_plan& p, int k) {
     if (k < 0 || k >= public_schedule_count()) return false;
-    if (k < 2 * N_SCHEDULES) {
-        p.sched = k % N_SCHEDULES;
-        p.map_mode = k / N_SCHEDULES;
-        return true;
-    }
-    if (!march_supported(p)) return false;
-    p.sched = N_SCHEDULES + (k - 2 * N_SCHEDULES);
-    p.map_mode = 0;
+    p.sched = k % N_SCHEDULES;
+    p.map_mode = k / N_SCHEDULES;
     return true;
 }
 
 int default_schedule(const vdwlb_plan& p) {
     (void)p;
-    return 1;  // 64 x 8
+    return 1;  // 64 x 8, non-temporal stores
 }
 
 bool graphs_enabled() {

@@ -98,9 +98,23 @@ __device__ __forceinline__ void pull_offsets(const Geometry& g, int x, int y, in
     o[8] = rp + xm;
 }
 
-// Element idx of a plane: a workgroup-uniform base pointer plus a 32-bit byte
-// offset (plans keep a plane below 2^28 elements), so the loads and stores
-// use a scalar base with a 32-bit vector offset.
+// State layout: nine planes, one per velocity i, each `plane` sites long,
+// and at each site the C components side by side:
+//     f_i^c(s) = f[(i plane + s) C + c].
+// The C components of one population at one site are then one vector of
+// C sizeof(T) bytes (a 16-byte load for C = 2 in FP64 or C = 4 in FP32).
+// Accesses use the workgroup-uniform base of plane i plus a 32-bit byte
+// offset s C sizeof(T) (plans keep a plane below 2^32 bytes), so loads and
+// stores take the scalar-base form with a 32-bit vector offset.
+template <typename T, int C>
+__device__ __forceinline__ const T* plane_base(const T* f, int i, int64_t plane) {
+    return f + (int64_t)i * plane * C;
+}
+template <typename T, int C>
+__device__ __forceinline__ T* plane_base(T* f, int i, int64_t plane) {
+    return f + (int64_t)i * plane * C;
+}
+
 template <typename T>
 __device__ __forceinline__ const T& at(const T* base, int idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
@@ -110,12 +124,51 @@ __device__ __forceinline__ T& at(T* base, int idx) {
     return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
 }
 
+// The C components at site s of one plane (a single vector access when C is
+// 2 or 4; plans require the state to be aligned to C sizeof(T) bytes).
+template <typename T, int C>
+__device__ __forceinline__ void load_site(const T* base, int s, T (&v)[C]) {
+    if constexpr (C == 2 || C == 4) {
+        typedef T V __attribute__((ext_vector_type(C)));
+        const V w = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) +
+                                                (uint32_t)s * (uint32_t)(C * sizeof(T)));
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = w[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = at(base, s * C + c);
+    }
+}
+
+template <typename T, int C, bool NTSTORE>
+__device__ __forceinline__ void store_site(T* base, int s, const T (&v)[C]) {
+    if constexpr (C == 2 || C == 4) {
+        typedef T V __attribute__((ext_vector_type(C)));
+        V w;
+#pragma unroll
+        for (int c = 0; c < C; ++c) w[c] = v[c];
+        V* dst = reinterpret_cast<V*>(reinterpret_cast<char*>(base) + (uint32_t)s * (uint32_t)(C * sizeof(T)));
+        if constexpr (NTSTORE) __builtin_nontemporal_store(w, dst);
+        else *dst = w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T& dst = at(base, s * C + c);
+            if constexpr (NTSTORE) __builtin_nontemporal_store(v[c], &dst);
+            else dst = v[c];
+        }
+    }
+}
+
 template <typename T, int C>
 __device__ __forceinline__ void pull(const T* __restrict__ f, const Geometry& g, const int (&o)[Q], T (&p)[C][Q]) {
 #pragma unroll
-    for (int c = 0; c < C; ++c)
+    for (int i = 0; i < Q; ++i) {
+        T v[C];
+        load_site<T, C>(plane_base<T, C>(f, i, g.plane), o[i], v);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) p[c][i] = at(f + (int64_t)(c * Q + i) * g.plane, o[i]);
+        for (int c = 0; c < C; ++c) p[c][i] = v[c];
+    }
 }
 
 // rho = sum_i f_i, summed in velocity order.
@@ -131,6 +184,15 @@ template <typename T>
 __device__ __forceinline__ void momentum(const T (&p)[Q], T& jx, T& jy) {
     jx = ((p[1] - p[3]) + (p[5] - p[6])) + (p[8] - p[7]);
     jy = ((p[2] - p[4]) + (p[5] + p[6])) - (p[7] + p[8]);
+}
+
+// Materialise v in registers at this point.  The compiler otherwise sinks
+// the momentum sums past the workgroup barriers to their use in the
+// collision and keeps all pulled populations live through the potential
+// phase, which costs far more registers than the moments.
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+    asm volatile("" : "+v"(v));
 }
 
 // Isotropic 9-point stencils on an LDS array with row stride S, centred at
@@ -152,7 +214,56 @@ __device__ __forceinline__ void grad9s(const T* a, int ex, int ey, T& gx, T& gy)
     gy = (T(4) * (r0[S] - r0[-S]) + ((ne + nw) - (sw + se))) * T(1.0 / 12.0);
 }
 
-__device__ __forceinline__ double dlog(double v) { return log(v); }
+// Reciprocal from the hardware estimate and two Newton steps
+// r <- r + r (1 - d r) (each step doubles the correct bits), about 1 ulp.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
+}
+
+// Natural logarithm in FP64.  With x = 2^e m, m in [sqrt(1/2), sqrt(2)),
+// ln x = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716, and
+// atanh(s) = s (1 + z/3 + z^2/5 + ...), z = s^2, summed to z^10 (the first
+// dropped term is below 2^-55 relative).  m - 1 is exact and m + 1 = d + dl
+// exactly, so one correction step makes s nearly correctly rounded; ln 2 is
+// split into a 32-bit head (e times it is exact) and a tail.  Worst case
+// about 1.5 ulp.  x <= 0 or NaN gives NaN, so finiteness checks catch it.
+__device__ __forceinline__ double dlog(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool low = m < 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
+    m = low ? m + m : m;
+    e = low ? e - 1 : e;
+    const double f = m - 1.0, d = m + 1.0, dl = m - (d - 1.0);
+    const double r = recip(d);
+    const double s0 = f * r;
+    double t = __builtin_fma(-s0, d, f);
+    t = __builtin_fma(-s0, dl, t);
+    const double s = __builtin_fma(r, t, s0);
+    const double z = s * s;
+    double P = 1.0 / 21.0;
+    P = __builtin_fma(P, z, 1.0 / 19.0);
+    P = __builtin_fma(P, z, 1.0 / 17.0);
+    P = __builtin_fma(P, z, 1.0 / 15.0);
+    P = __builtin_fma(P, z, 1.0 / 13.0);
+    P = __builtin_fma(P, z, 1.0 / 11.0);
+    P = __builtin_fma(P, z, 1.0 / 9.0);
+    P = __builtin_fma(P, z, 1.0 / 7.0);
+    P = __builtin_fma(P, z, 1.0 / 5.0);
+    P = __builtin_fma(P, z, 1.0 / 3.0);
+    const double u = s + s;
+    const double lm = __builtin_fma(u * z, P, u);
+    const double ed = (double)e;
+    const double res = __builtin_fma(ed, 0x1.62e42ff000000p-1, __builtin_fma(ed, -0x1.718432a1b0e26p-35, lm));
+    return x > 0.0 ? res : __builtin_nan("");
+}
 __device__ __forceinline__ float dlog(float v) { return logf(v); }
 
 template <typename T>
@@ -173,7 +284,7 @@ __device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], 
         tot += rho[c];
     }
     const T free_vol = T(1) - eta;
-    const T inv = T(1) / free_vol;
+    const T inv = recip(free_vol);
     bool ok = free_vol > T(0);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -327,13 +438,10 @@ __device__ __forceinline__ void pull_density(const T* __restrict__ f, const Geom
                                              int stride) {
     int o[Q];
     pull_offsets(g, x, y, o);
+    T q[C][Q];
+    pull<T, C>(f, g, o, q);
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        T q[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) q[i] = at(f + (int64_t)(c * Q + i) * g.plane, o[i]);
-        dst[c * stride] = density<T>(q);
-    }
+    for (int c = 0; c < C; ++c) dst[c * stride] = density<T>(q[c]);
 }
 
 // Friction, collision and store of one site whose pulled populations p,
@@ -344,7 +452,7 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
                                               T* __restrict__ fout, int64_t plane, int s) {
     T ri[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) ri[c] = T(1) / rho[c];
+    for (int c = 0; c < C; ++c) ri[c] = recip(rho[c]);
     if constexpr (C > 1) {
         // W = lambda rho rho' / (rho + rho') = lambda / (1/rho + 1/rho')
         T W[C][C];
@@ -355,19 +463,19 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) / (ri[c] + ri[d]);
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) * recip(ri[c] + ri[d]);
         friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
         friction<T, C>(rho, ri, jy, gy, W, T(k.fk));
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
+    for (int c = 0; c < C; ++c)
         collide<T, TAU1>(p[c], rho[c], ri[c], jx[c], jy[c], gx[c], gy[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T& dst = at(fout + (int64_t)(c * Q + i) * plane, s);
-            if constexpr (NTSTORE) __builtin_nontemporal_store(p[c][i], &dst);
-            else dst = p[c][i];
-        }
+    for (int i = 0; i < Q; ++i) {
+        T v[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = p[c][i];
+        store_site<T, C, NTSTORE>(plane_base<T, C>(fout, i, plane), s, v);
     }
 }
 
@@ -492,6 +600,10 @@ k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k
     for (int c = 0; c < C; ++c) {
         rho[c] = density<T>(p[c]);
         momentum<T>(p[c], jx[c], jy[c]);
+        if constexpr (TAU1 || C > 2) {  // fewer live registers (measured)
+            pin(jx[c]);
+            pin(jy[c]);
+        }
         s_rho[c][(ly + 2) * EX + lx + 2] = rho[c];
     }
     for (int r = threadIdx.x; r < RING; r += NT) {
@@ -542,21 +654,26 @@ __global__ void k_init(T* __restrict__ f, const T* __restrict__ rho, const T* __
     const int n = g.nx * g.ny;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
+    T p[C][Q];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const T r = rho[(int64_t)c * n + s];
-        T p[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) p[i] = T(0);
+        for (int i = 0; i < Q; ++i) p[c][i] = T(0);
         T jx = T(0), jy = T(0);
         if (mom) {
             jx = mom[(int64_t)(2 * c) * n + s];
             jy = mom[(int64_t)(2 * c + 1) * n + s];
         }
         // collide with omega = 1 and no force from p = 0 gives exactly f^0
-        collide<T>(p, r, T(1) / r, jx, jy, T(0), T(0), T(0), T(1), T(0), T(0));
+        collide<T>(p[c], r, T(1) / r, jx, jy, T(0), T(0), T(0), T(1), T(0), T(0));
+    }
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[(int64_t)(c * Q + i) * g.plane + s] = p[i];
+    for (int i = 0; i < Q; ++i) {
+        T v[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = p[c][i];
+        store_site<T, C, false>(plane_base<T, C>(f, i, g.plane), s, v);
     }
 }
 

@@ -114,19 +114,20 @@ class Lattice:
 
     @property
     def state(self) -> torch.Tensor:
-        """The current population buffer viewed as [C, 9, plane]."""
-        return self.buf[self.cur].view(self.C, 9, self.plan.plane)
+        """The current population buffer in its storage layout [9, plane, C]
+        (velocity planes of sites, the components of a site adjacent)."""
+        return self.buf[self.cur].view(9, self.plan.plane, self.C)
 
     def state_sites(self) -> torch.Tensor:
         """Populations as [C, 9, ny, nx] (a copy without the plane padding)."""
         n = self.nx * self.ny
-        return self.state[:, :, :n].reshape(self.C, 9, self.ny, self.nx).clone()
+        return self.state[:, :n, :].permute(2, 0, 1).reshape(self.C, 9, self.ny, self.nx).clone()
 
     def set_state(self, f) -> None:
         """Load populations given as [C, 9, ny, nx] into the current buffer."""
         n = self.nx * self.ny
         t = self._field(f, (self.C, 9, self.ny, self.nx)).reshape(self.C, 9, n)
-        self.state[:, :, :n].copy_(t)
+        self.state[:, :n, :].copy_(t.permute(1, 2, 0))
 
     def moments(self, want_mu=True, want_p=True, stream=None):
         """rho [C,ny,nx], mom [C,2,ny,nx], mu [C,ny,nx] or None, p [ny,nx] or None.

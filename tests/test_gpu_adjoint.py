@@ -58,14 +58,15 @@ def make_state(orc, P, nx, ny, seed):
 
 
 def pad(t_np, plane):
+    """[C, 9, ny, nx] -> a device state buffer [9, plane, C]."""
     C, Q, ny, nx = t_np.shape
-    out = np.zeros((C, Q, plane))
-    out[:, :, :nx * ny] = t_np.reshape(C, Q, nx * ny)
+    out = np.zeros((Q, plane, C))
+    out[:, :nx * ny, :] = t_np.reshape(C, Q, nx * ny).transpose(1, 2, 0)
     return torch.as_tensor(out.reshape(-1), device="cuda")
 
 
 def unpad(t, C, ny, nx, plane):
-    return t.view(C, 9, plane)[:, :, :nx * ny].reshape(C, 9, ny, nx).cpu().numpy()
+    return t.view(9, plane, C)[:, :nx * ny, :].permute(2, 0, 1).reshape(C, 9, ny, nx).cpu().numpy()
 
 
 def gpu_vjp(lattice, V, P, f, wbar, nsteps=1):

@@ -70,7 +70,7 @@ def test_spinodal_small_f32_1000_steps(gpu, orc):
     assert rel_err(np_(rho), rho_ref) <= 1e-4
 
 
-N_SCHED = 34
+N_SCHED = 28
 
 
 @pytest.mark.parametrize("sched", range(N_SCHED))
@@ -114,14 +114,16 @@ def test_schedules_bitwise_identical(gpu):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("sched", [None, 21])
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (5, 1), (3, 7), (9, 4), (70, 3)])
-def test_tiny_and_thin_lattices(gpu, orc, nx, ny):
-    """Extents smaller than the stencil reach wrap several times."""
+def test_tiny_and_thin_lattices(gpu, orc, nx, ny, sched):
+    """Extents smaller than the stencil reach wrap several times (default
+    schedule and the band-ordered 32 x 16 one)."""
     w = I.spinodal_small(0)
     w.nx, w.ny = nx, ny
     w.rho = np.random.default_rng(nx * 31 + ny).uniform(2.55, 2.7, (2, ny, nx))
     ref, _ = oracle_run(orc, w, 12)
-    lat = gpu_run(gpu, w, 12)
+    lat = gpu_run(gpu, w, 12, sched=sched)
     np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-13)
 
 
@@ -239,6 +241,26 @@ def test_invalid_arguments(gpu):
     with pytest.raises(V.VdwlbError) as ei:
         gpu.Lattice(8, 8, big.kT, big.a, big.b, big.kappa)
     assert ei.value.status == V.E_UNSUPPORTED
+
+
+def test_misaligned_state_rejected(gpu):
+    """C = 2 in FP64 reads a site's two components as one 16-byte vector, so
+    a state buffer off by one element is refused before any launch."""
+    from paper_1805_07251_amd import vdwlb as V
+
+    w = I.spinodal_small(0, n=16)
+    lat = gpu.Lattice.from_workload(w)
+    n = lat.plan.state_elems
+    raw = torch.zeros(2 * n + 2, dtype=torch.float64, device="cuda")
+    a, b = raw.data_ptr() + 8, raw.data_ptr() + 8 * (n + 2)
+    lib = V.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.vdwlb_step(lat.plan.handle, a, b, 1, s, None) == V.E_INVALID_ARG
+    rho = torch.as_tensor(w.rho, device="cuda")
+    assert lib.vdwlb_init(lat.plan.handle, a, rho.data_ptr(), None, s) == V.E_INVALID_ARG
+    assert lib.vdwlb_moments(lat.plan.handle, a, rho.data_ptr(), None, None, None, s) == V.E_INVALID_ARG
+    # aligned pointers into the same allocation work
+    assert lib.vdwlb_init(lat.plan.handle, raw.data_ptr(), rho.data_ptr(), None, s) == V.OK
 
 
 def test_autotune_keeps_results(gpu):
