@@ -108,10 +108,11 @@ def copy_gbs(nbytes=1 << 30, reps=20):
     return 2 * nbytes / secs / 1e9
 
 
-def traffic_from_profiles(kernel_key: str):
-    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
-    recorded in profiles/ together with the hash of the sweep
-    source they were taken on; None when the source has changed since."""
+def traffic_from_profiles(schedule: int):
+    """HBM bytes per launch of the sweep kernel under `schedule`, measured
+    with rocprofv3 FETCH_SIZE / WRITE_SIZE and recorded in profiles/ together
+    with the hash of the sweep source they were taken on; None when the
+    source has changed since or the schedule was not profiled."""
     path = os.path.join(ROOT, "profiles", "k_sweep_spinodal2048_f64_traffic.md")
     if not os.path.exists(path):
         return None
@@ -119,7 +120,7 @@ def traffic_from_profiles(kernel_key: str):
     m = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     if not m or m.group(1) != sweep_source_hash():
         return None
-    m = re.search(rf"traffic_bytes_per_launch:\s*{re.escape(kernel_key)}\s*=\s*([0-9.eE+]+)", txt)
+    m = re.search(rf"traffic_bytes_per_launch:\s*schedule {schedule}\s*=\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
 
@@ -299,7 +300,7 @@ def main():
         return
     sites = w.nx * w.ny
     achieved = head["gbs"]
-    traffic = traffic_from_profiles("k_sweep<double, 2>")
+    traffic = traffic_from_profiles(head["schedule"])
     out = {
         "metric": METRIC,
         "value": head["mlups_x_c"],
