@@ -162,8 +162,9 @@ int32_t vdwlb_schedule_count(const vdwlb_plan* plan);
 /* Select schedule k (0 <= k < vdwlb_schedule_count) for later steps. */
 vdwlb_status vdwlb_set_schedule(vdwlb_plan* plan, int32_t k);
 
-/* Time every schedule on this plan's lattice (reads fA, overwrites fB), keep
- * the fastest and report it in *chosen (may be NULL).  Synchronous. */
+/* Time every schedule on this plan's lattice (reads fA, overwrites fB),
+ * re-time the four fastest with more launches, keep the fastest and report it
+ * in *chosen (may be NULL).  Synchronous. */
 vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* stream, int32_t* chosen);
 
 /* Liquid-gas coexistence of one van der Waals component (Eqs. tetcr, rhocr

@@ -218,36 +218,52 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     HIP_TRY(hipEventCreate(&e1));
     const int64_t sites = (int64_t)p->nx * p->ny;
     const int reps = sites >= (1 << 20) ? 10 : 50;
-    float best = 1e30f;
     const int keep_s = p->sched, keep_m = p->map_mode;
-    int best_k = -1;
-    for (int k = 0; k < public_schedule_count(); ++k) {
-        if (!apply_public_schedule(*p, k)) continue;  // not available for this lattice
+    // average launch time of public schedule k over n launches (after 3 warm-up launches)
+    auto time_k = [&](int k, int n, float& ms) -> hipError_t {
+        apply_public_schedule(*p, k);
         hipError_t e = hipSuccess;
         for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch_sweep(*p, fA, fB, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_sweep(*p, fA, fB, s);
+        for (int r = 0; r < n && e == hipSuccess; ++r) e = launch_sweep(*p, fA, fB, s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            p->sched = keep_s;
-            p->map_mode = keep_m;
-            return dev_fail(e, "autotune");
-        }
-        if (ms < best) {
-            best = ms;
-            best_k = k;
-        }
+        ms /= (float)n;
+        return e;
+    };
+    // first pass over every schedule, then the four fastest again, twice
+    // each in alternation, with four times the launches (single short timings
+    // of schedules within a few per cent of each other are noise)
+    std::vector<std::pair<float, int>> t;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < public_schedule_count() && e == hipSuccess; ++k) {
+        float ms = 0;
+        e = time_k(k, reps, ms);
+        t.push_back({ms, k});
     }
+    std::sort(t.begin(), t.end());
+    const int top = (int)std::min<size_t>(4, t.size());
+    std::vector<float> acc(top, 0.0f);
+    for (int round = 0; round < 2 && e == hipSuccess; ++round)
+        for (int j = 0; j < top && e == hipSuccess; ++j) {
+            float ms = 0;
+            e = time_k(t[j].second, 4 * reps, ms);
+            acc[j] += ms;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_graph(*p);
     p->sched = keep_s;
     p->map_mode = keep_m;
+    if (e != hipSuccess) return dev_fail(e, "autotune");
+    int best_k = -1;
+    float best = 0;
+    for (int j = 0; j < top; ++j)
+        if (best_k < 0 || acc[j] < best) {
+            best = acc[j];
+            best_k = t[j].second;
+        }
     if (best_k >= 0) apply_public_schedule(*p, best_k);
     if (chosen) *chosen = best_k;
     return VDWLB_OK;

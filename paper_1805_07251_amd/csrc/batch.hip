@@ -19,6 +19,98 @@
 
 namespace vdwlb {
 
+// LDS footprint of one full-height strip: the NY rows of the lattice at rows
+// 1..NY, a copy of the last lattice row at row 0 and of the first at row
+// NY + 1, so the periodic y neighbours sit at fixed strides; TX
+// columns plus an x ring of 2 (density) / 1 (potential).
+template <int TX, int NY>
+struct StripLds {
+    static constexpr int EX = TX + 4, MX = TX + 2, RY = NY + 2;
+    static constexpr int SR = EX * RY, SP = MX * RY;
+};
+
+// Store v at padded row `row` (1..NY) of column e, and at its periodic copy.
+template <typename T, int NY, int S>
+__device__ __forceinline__ void put_wrapped(T* plane, int row, int e, T v) {
+    plane[row * S + e] = v;
+    if (row == 1) plane[(NY + 1) * S + e] = v;
+    if (row == NY) plane[e] = v;
+}
+
+// One time step of the TX-column strip starting at x0 of a lattice whose
+// height is exactly NY (quasi-1-D lattices): the rows wrap inside LDS, so
+// only the x ring is recomputed.  Executed by TX * NY threads.  Every site
+// goes through the same arithmetic as in the plain sweep (same functions and
+// stencil expressions), so results are bit-identical to it.
+template <typename T, int C, int TX, int NY, bool NTSTORE, bool TAU1>
+__device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restrict__ fout, const Geometry& g,
+                                           const Coeffs<C>& k, int x0, T* s_rho, T* s_phi) {
+    using L = StripLds<TX, NY>;
+    constexpr int NT = TX * NY, EX = L::EX, MX = L::MX;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx;
+    const int xs = wrapc(x, g.nx, g.wrap_general);
+
+    T p[C][Q];
+    int o[Q];
+    pull_offsets(g, xs, ly, o);
+    pull<T, C>(fin, g, o, p);
+    T rho[C], jx[C], jy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = density<T>(p[c]);
+        momentum<T>(p[c], jx[c], jy[c]);
+        if constexpr (TAU1 || C > 2) {  // as in k_sweep
+            pin(jx[c]);
+            pin(jy[c]);
+        }
+        put_wrapped<T, NY, EX>(s_rho + c * L::SR, ly + 1, lx + 2, rho[c]);
+    }
+    for (int r = threadIdx.x; r < 4 * NY; r += NT) {
+        const int row = r >> 2, kq = r & 3;
+        const int ex = kq < 2 ? kq : EX - 4 + kq;
+        T q[C];
+        pull_density<T, C>(fin, g, wrapc(x0 - 2 + ex, g.nx, g.wrap_general), row, q, 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) put_wrapped<T, NY, EX>(s_rho + c * L::SR, row + 1, ex, q[c]);
+    }
+    __syncthreads();
+
+    bool bad = false;
+    for (int m = threadIdx.x; m < MX * NY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        T r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c * L::SR + (my + 1) * EX + mx + 1];
+            l[c] = lap9s<T, EX>(s_rho + c * L::SR, mx + 1, my + 1);
+        }
+        bad |= !potential<T, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) put_wrapped<T, NY, MX>(s_phi + c * L::SP, my + 1, mx, ph[c]);
+    }
+    __syncthreads();
+
+    if (x < g.nx) {
+        T gx[C], gy[C], lap[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T px, py, rx, ry;
+            grad9s<T, MX>(s_phi + c * L::SP, lx + 1, ly + 1, px, py);
+            grad9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1, rx, ry);
+            lap[c] = lap9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1);
+            gx[c] = -rho[c] * px;
+            gy[c] = -rho[c] * py;
+            if (k.force == 0) {
+                gx[c] += T(THETA) * rx;
+                gy[c] += T(THETA) * ry;
+            }
+        }
+        collide_store<T, C, NTSTORE, TAU1>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, ly * g.nx + x);
+    }
+    return bad;
+}
+
 template <int C>
 struct Instance {
     Geometry g;
@@ -31,7 +123,10 @@ __global__ void k_reset_counter(int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-template <typename T, int C, int TX, int NY>
+// TAUS: 1 when every instance has tau = 1, 2 when none has, 0 for a mix
+// (per-instance branch; the register budget is then that of the general
+// collision).
+template <typename T, int C, int TX, int NY, int TAUS>
 __global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict__ inst, const int* __restrict__ order,
                                                     int n, T* poolA, T* poolB, int nsteps, int* counter,
                                                     int* __restrict__ status) {
@@ -55,7 +150,7 @@ __global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict
         g.wrap_general = g.nx < TX + 8 ? 1 : 0;
         T* A = poolA + I.offset;
         T* B = poolB + I.offset;
-        const bool tau1 = I.k.omega == 1.0;
+        const bool tau1 = TAUS == 1 || (TAUS == 0 && I.k.omega == 1.0);
         int fail = 0;
         for (int t = 0; t < nsteps; ++t) {
             const T* src = (t & 1) ? B : A;
@@ -63,7 +158,11 @@ __global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict
             bool bad = false;
             for (int x0 = 0; x0 < g.nx; x0 += TX) {
                 // same collision form as the plain sweep of this instance (tau = 1 or not)
-                if (tau1)
+                if constexpr (TAUS == 1)
+                    bad |= strip_step<T, C, TX, NY, false, true>(src, dst, g, I.k, x0, s_rho, s_phi);
+                else if constexpr (TAUS == 2)
+                    bad |= strip_step<T, C, TX, NY, false, false>(src, dst, g, I.k, x0, s_rho, s_phi);
+                else if (tau1)
                     bad |= strip_step<T, C, TX, NY, false, true>(src, dst, g, I.k, x0, s_rho, s_phi);
                 else
                     bad |= strip_step<T, C, TX, NY, false, false>(src, dst, g, I.k, x0, s_rho, s_phi);
@@ -124,6 +223,7 @@ using namespace vdwlb;
 
 struct vdwlb_batch {
     int n = 0, C = 0, dtype = 0, ny = 0;
+    int taus = 0;  // 1: every instance has tau = 1, 2: none has, 0: mixed
     std::vector<int64_t> offset, rho_offset, sites;
     int64_t pool_elems = 0, rho_elems = 0;
     void* d_inst = nullptr;  // Instance<C>[n]
@@ -145,8 +245,16 @@ vdwlb_status bfail(hipError_t e, const char* where) { return set_device_error(e,
 
 template <typename T, int C, int TX, int NY>
 hipError_t launch_batch_shape(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch<T, C, TX, NY>), dim3(blocks), dim3(TX * NY), 0, s, (const Instance<C>*)b.d_inst,
-                       b.d_order, b.n, (T*)A, (T*)B, nsteps, b.d_counter, b.d_status);
+    auto* inst = (const Instance<C>*)b.d_inst;
+    if (b.taus == 1)
+        hipLaunchKernelGGL((k_batch<T, C, TX, NY, 1>), dim3(blocks), dim3(TX * NY), 0, s, inst, b.d_order, b.n, (T*)A,
+                           (T*)B, nsteps, b.d_counter, b.d_status);
+    else if (b.taus == 2)
+        hipLaunchKernelGGL((k_batch<T, C, TX, NY, 2>), dim3(blocks), dim3(TX * NY), 0, s, inst, b.d_order, b.n, (T*)A,
+                           (T*)B, nsteps, b.d_counter, b.d_status);
+    else
+        hipLaunchKernelGGL((k_batch<T, C, TX, NY, 0>), dim3(blocks), dim3(TX * NY), 0, s, inst, b.d_order, b.n, (T*)A,
+                           (T*)B, nsteps, b.d_counter, b.d_status);
     return hipGetLastError();
 }
 
@@ -284,6 +392,9 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
     b->C = C;
     b->dtype = dtype;
     b->ny = ny;
+    int n_tau1 = 0;
+    for (const vdwlb_plan& q : plans) n_tau1 += q.tau == 1.0 ? 1 : 0;
+    b->taus = n_tau1 == n ? 1 : (n_tau1 == 0 ? 2 : 0);
     b->offset.resize(n);
     b->rho_offset.resize(n);
     b->sites.resize(n);

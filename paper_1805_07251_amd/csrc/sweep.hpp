@@ -479,94 +479,6 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
     }
 }
 
-// LDS footprint of one full-height strip: the NY rows of the lattice at rows
-// 1..NY, a copy of the last lattice row at row 0 and of the first at row
-// NY + 1, so the periodic y neighbours sit at fixed strides; TX
-// columns plus an x ring of 2 (density) / 1 (potential).
-template <int TX, int NY>
-struct StripLds {
-    static constexpr int EX = TX + 4, MX = TX + 2, RY = NY + 2;
-    static constexpr int SR = EX * RY, SP = MX * RY;
-};
-
-// Store v at padded row `row` (1..NY) of column e, and at its periodic copy.
-template <typename T, int NY, int S>
-__device__ __forceinline__ void put_wrapped(T* plane, int row, int e, T v) {
-    plane[row * S + e] = v;
-    if (row == 1) plane[(NY + 1) * S + e] = v;
-    if (row == NY) plane[e] = v;
-}
-
-// One time step of the TX-column strip starting at x0 of a lattice whose
-// height is exactly NY (quasi-1-D lattices): the rows wrap inside LDS, so
-// only the x ring is recomputed.  Executed by TX * NY threads.  Every site
-// goes through the same arithmetic as in the plain sweep (same functions and
-// stencil expressions), so results are bit-identical to it.
-template <typename T, int C, int TX, int NY, bool NTSTORE, bool TAU1>
-__device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restrict__ fout, const Geometry& g,
-                                           const Coeffs<C>& k, int x0, T* s_rho, T* s_phi) {
-    using L = StripLds<TX, NY>;
-    constexpr int NT = TX * NY, EX = L::EX, MX = L::MX;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = x0 + lx;
-    const int xs = wrapc(x, g.nx, g.wrap_general);
-
-    T p[C][Q];
-    int o[Q];
-    pull_offsets(g, xs, ly, o);
-    pull<T, C>(fin, g, o, p);
-    T rho[C], jx[C], jy[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        rho[c] = density<T>(p[c]);
-        momentum<T>(p[c], jx[c], jy[c]);
-        put_wrapped<T, NY, EX>(s_rho + c * L::SR, ly + 1, lx + 2, rho[c]);
-    }
-    for (int r = threadIdx.x; r < 4 * NY; r += NT) {
-        const int row = r >> 2, kq = r & 3;
-        const int ex = kq < 2 ? kq : EX - 4 + kq;
-        T q[C];
-        pull_density<T, C>(fin, g, wrapc(x0 - 2 + ex, g.nx, g.wrap_general), row, q, 1);
-#pragma unroll
-        for (int c = 0; c < C; ++c) put_wrapped<T, NY, EX>(s_rho + c * L::SR, row + 1, ex, q[c]);
-    }
-    __syncthreads();
-
-    bool bad = false;
-    for (int m = threadIdx.x; m < MX * NY; m += NT) {
-        const int my = m / MX, mx = m - my * MX;
-        T r[C], l[C], ph[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            r[c] = s_rho[c * L::SR + (my + 1) * EX + mx + 1];
-            l[c] = lap9s<T, EX>(s_rho + c * L::SR, mx + 1, my + 1);
-        }
-        bad |= !potential<T, C>(r, l, k, ph);
-#pragma unroll
-        for (int c = 0; c < C; ++c) put_wrapped<T, NY, MX>(s_phi + c * L::SP, my + 1, mx, ph[c]);
-    }
-    __syncthreads();
-
-    if (x < g.nx) {
-        T gx[C], gy[C], lap[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            T px, py, rx, ry;
-            grad9s<T, MX>(s_phi + c * L::SP, lx + 1, ly + 1, px, py);
-            grad9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1, rx, ry);
-            lap[c] = lap9s<T, EX>(s_rho + c * L::SR, lx + 2, ly + 1);
-            gx[c] = -rho[c] * px;
-            gy[c] = -rho[c] * py;
-            if (k.force == 0) {
-                gx[c] += T(THETA) * rx;
-                gy[c] += T(THETA) * ry;
-            }
-        }
-        collide_store<T, C, NTSTORE, TAU1>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, ly * g.nx + x);
-    }
-    return bad;
-}
-
 // The plain sweep: one launch per time step, one workgroup per TX x TY tile.
 // Phase 1 pulls the 9C populations of each interior site into registers
 // (reused by the collision unless tau = 1) and the densities of the radius-2 ring around the

@@ -60,6 +60,22 @@ def test_batch_matches_plain_bitwise(gpu, threads):
             assert np.array_equal(got, ref), k
 
 
+@pytest.mark.parametrize("taus", ["mixed", "none"])
+def test_batch_tau_mix_matches_plain(gpu, taus):
+    """Instances with tau != 1 (all of them, or every other one) take the
+    general collision; each must still equal its plain run bit for bit."""
+    batch, lattice = gpu
+    ws = slabs(6, range(6), lmax=300)
+    for k, w in enumerate(ws):
+        if taus == "none" or k % 2 == 1:
+            w.tau = 0.8 + 0.05 * k
+    b = batch_run(batch, ws, 30)
+    st = b.status()
+    for k, w in enumerate(ws):
+        assert st[k] == 0, k
+        assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, w, 30)), k
+
+
 def test_batch_against_oracle(gpu, orc):
     batch, _ = gpu
     ws = slabs(1, range(3), lmax=40)
