@@ -128,7 +128,7 @@ def sweep_source_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for fn in ("sweep.hpp", "launch.hpp"):
+    for fn in ("sweep.hpp", "schedules.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1805_07251_amd", "csrc", fn), "rb").read())
     return h.hexdigest()
 
@@ -263,7 +263,7 @@ def adjoint_leg(seed):
     }
 
 
-def cpu_baseline(w, steps=5):
+def cpu_baseline(w, steps=8):
     """The CPU oracle on the same workload for a few steps (single thread)."""
     from oracle import oracle as O
 
