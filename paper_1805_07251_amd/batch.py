@@ -29,13 +29,14 @@ class Batch:
         for k, w in enumerate(workloads):
             arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (w.a, w.b, w.kappa, w.lam)]
             self._keep.append(arrs)
-            descs[k] = V.Desc(2, w.nx, w.ny, w.C, self.dtype, w.force, float(w.kT), float(w.tau),
+            descs[k] = V.Desc(getattr(w, "dim", 2), w.nx, w.ny, w.C, self.dtype, w.force, float(w.kT), float(w.tau),
                               float(w.gamma_mu), *[dptr(x) for x in arrs])
         h = ctypes.c_void_p()
         V.check(V.lib().vdwlb_batch_create(self.n, descs, ctypes.byref(h)), "vdwlb_batch_create")
         self.handle = h
         self.shapes = [(w.C, w.ny, w.nx) for w in workloads]
         self.C = workloads[0].C
+        self.Q = 3 if getattr(workloads[0], "dim", 2) == 1 else 9
         self.sites = np.array([w.nx * w.ny for w in workloads], dtype=np.int64)
         nbytes = int(V.lib().vdwlb_batch_state_bytes(h))
         elems = nbytes // torch.tensor([], dtype=self.torch_dtype).element_size()
@@ -85,8 +86,9 @@ class Batch:
         return [out[o:o + int(np.prod(s))].view(*s) for o, s in zip(self.rho_offsets, self.shapes)]
 
     def state(self, k) -> torch.Tensor:
-        """Populations of instance k as [C, 9, ny, nx] (a copy)."""
+        """Populations of instance k as [C, Q, ny, nx] (a copy)."""
         C, ny, nx = self.shapes[k]
+        Q = self.Q
         plane = (nx * ny + 63) // 64 * 64
-        v = self.pools[self.cur][self.offsets[k]:self.offsets[k] + 9 * C * plane].view(9, plane, C)
-        return v[:, :nx * ny, :].permute(2, 0, 1).reshape(C, 9, ny, nx).clone()
+        v = self.pools[self.cur][self.offsets[k]:self.offsets[k] + Q * C * plane].view(Q, plane, C)
+        return v[:, :nx * ny, :].permute(2, 0, 1).reshape(C, Q, ny, nx).clone()

@@ -447,7 +447,7 @@ size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* p, int32_t nsteps) {
 vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const void* mom_bar, void* fbar,
                                    void* stream) {
     if (!p || !fbar || (!rho_bar && !mom_bar) || !state_aligned(*p, fbar)) return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
+    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     const Geometry g = make_geometry(*p, adj::TX, adj::TY);
     const int nb = (int)(((int64_t)p->nx * p->ny + adj::BLK - 1) / adj::BLK);
     hipError_t e = hipMemsetAsync(fbar, 0, vdwlb_state_bytes(p), (hipStream_t)stream);
@@ -467,7 +467,7 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
     if (!p || !f_ckpt || !fbar_io || !workspace || !pbar_accum || nsteps < 1) return VDWLB_E_INVALID_ARG;
     if (!state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io) || !state_aligned(*p, workspace))
         return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2) return VDWLB_E_UNSUPPORTED;
+    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const Layout L = layout(*p, nsteps);
     double* ws = (double*)workspace;

@@ -67,7 +67,7 @@ int32_t validate_desc(const vdwlb_desc* d) {
             }
         }
     }
-    if (d->dim != 2) return VDWLB_E_UNSUPPORTED;
+    if (d->dim == 1 && d->ny != 1) return VDWLB_E_INVALID_ARG;  // D1Q3 lattices are nx x 1
     if (C > VDWLB_MAX_COMPONENTS) return VDWLB_E_UNSUPPORTED;
     return VDWLB_OK;
 }
@@ -149,7 +149,7 @@ int64_t vdwlb_plane_elems(const vdwlb_plan* p) { return p ? p->plane : 0; }
 
 size_t vdwlb_state_bytes(const vdwlb_plan* p) {
     if (!p) return 0;
-    return (size_t)9 * p->C * (size_t)p->plane * (p->dtype == VDWLB_F64 ? 8 : 4);
+    return (size_t)(p->dim == 1 ? 3 : 9) * p->C * (size_t)p->plane * (p->dtype == VDWLB_F64 ? 8 : 4);
 }
 
 vdwlb_status vdwlb_init(vdwlb_plan* p, void* f, const void* rho, const void* mom, void* stream) {
@@ -199,7 +199,7 @@ vdwlb_status vdwlb_moments(vdwlb_plan* p, const void* f, void* rho, void* mom, v
     return vdwlb_sync_status(p, stream);
 }
 
-int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? public_schedule_count() : 0; }
+int32_t vdwlb_schedule_count(const vdwlb_plan* p) { return p ? public_schedule_count(*p) : 0; }
 
 vdwlb_status vdwlb_set_schedule(vdwlb_plan* p, int32_t k) {
     if (!p) return VDWLB_E_INVALID_ARG;
@@ -237,7 +237,7 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     // of schedules within a few per cent of each other are noise)
     std::vector<std::pair<float, int>> t;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < public_schedule_count() && e == hipSuccess; ++k) {
+    for (int k = 0; k < public_schedule_count(*p) && e == hipSuccess; ++k) {
         float ms = 0;
         e = time_k(k, reps, ms);
         t.push_back({ms, k});

@@ -119,6 +119,35 @@ struct Instance {
     Coeffs<C> k;
 };
 
+// Friction and D1Q3 collision of one site, the new populations written to
+// the LDS state [i][c][x] (same arithmetic as collide_store1).
+template <typename T, int C, bool TAU1>
+__device__ __forceinline__ void collide_lds1(T (&p)[C][Q1], const T (&rho)[C], T (&jx)[C], T (&gx)[C],
+                                             const T (&lap)[C], const Coeffs<C>& k, T* sf, int lmax, int x) {
+    T ri[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ri[c] = recip(rho[c]);
+    if constexpr (C > 1) {
+        T W[C][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = 0; d < C; ++d) W[c][d] = T(0);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) * recip(ri[c] + ri[d]);
+        friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T q[Q1] = {p[c][0], p[c][1], p[c][2]};
+        collide1<T, TAU1>(q, rho[c], ri[c], jx[c], gx[c], lap[c], T(k.omega), T(k.cG), T(k.cL));
+#pragma unroll
+        for (int i = 0; i < Q1; ++i) sf[(i * C + c) * lmax + x] = q[i];
+    }
+}
+
 __global__ void k_reset_counter(int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
@@ -180,6 +209,132 @@ __global__ void __launch_bounds__(TX * NY) k_batch(const Instance<C>* __restrict
     }
 }
 
+// Batched D1Q3 sweep with every instance resident on chip: a workgroup loads
+// an instance's state into LDS, runs all its steps there (the lattice wraps
+// inside LDS, so no halo is ever re-read) and writes the final state back.
+// LDS holds f [3][C][lmax], rho [C][lmax] and phi [C][lmax]; each of the 256
+// threads owns the sites tid + k 256, k < SPT, and keeps their pulled
+// populations and moments in registers between the phases.  The per-site
+// arithmetic is that of the plain D1Q3 sweep (same functions), so results
+// are bit-identical to it.  The final state goes to poolA for an even step
+// count and to poolB for an odd one, as with ping-pong buffers.
+constexpr int B1_THREADS = 256;
+
+template <typename T, int C, int SPT, int TAUS>
+__global__ void __launch_bounds__(B1_THREADS) k_batch1(const Instance<C>* __restrict__ inst,
+                                                        const int* __restrict__ order, int n, T* poolA, T* poolB,
+                                                        int nsteps, int lmax, int* counter, int* __restrict__ status) {
+    constexpr int NT = B1_THREADS;
+    extern __shared__ __align__(16) unsigned char b1_smem[];
+    T* sf = reinterpret_cast<T*>(b1_smem);  // [i][c][x]
+    T* sr = sf + Q1 * C * lmax;             // [c][x]
+    T* sp = sr + C * lmax;                  // [c][x]
+    __shared__ int s_job, s_bad;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            s_job = atomicAdd(counter, 1);
+            s_bad = 0;
+        }
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        if (job >= n) return;  // uniform: the queue is drained
+        const int id = __builtin_amdgcn_readfirstlane(order[job]);
+        const Instance<C>& I = inst[id];
+        const int L = I.g.nx;
+        const int64_t plane = I.g.plane;
+        const bool tau1 = TAUS == 1 || (TAUS == 0 && I.k.omega == 1.0);
+        for (int x = tid; x < L; x += NT)
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) {
+                T v[C];
+                load_site<T, C>(plane_base<T, C>(poolA + I.offset, i, plane), x, v);
+#pragma unroll
+                for (int c = 0; c < C; ++c) sf[(i * C + c) * lmax + x] = v[c];
+            }
+        __syncthreads();
+        int fail = 0;
+        for (int t = 0; t < nsteps; ++t) {
+            T p[SPT][C][Q1], rho[SPT][C], jx[SPT][C];
+            // phase 1: pull from LDS, moments
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int x = tid + k * NT;
+                if (x < L) {
+                    const int xm = x == 0 ? L - 1 : x - 1, xp = x + 1 == L ? 0 : x + 1;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        p[k][c][0] = sf[(0 * C + c) * lmax + x];
+                        p[k][c][1] = sf[(1 * C + c) * lmax + xm];
+                        p[k][c][2] = sf[(2 * C + c) * lmax + xp];
+                        rho[k][c] = density1<T>(p[k][c]);
+                        jx[k][c] = p[k][c][1] - p[k][c][2];
+                        sr[c * lmax + x] = rho[k][c];
+                    }
+                }
+            }
+            __syncthreads();
+            // phase 2: potential at the own sites
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int x = tid + k * NT;
+                if (x < L) {
+                    const int xm = x == 0 ? L - 1 : x - 1, xp = x + 1 == L ? 0 : x + 1;
+                    T r[C], l[C], ph[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        r[c] = sr[c * lmax + x];
+                        l[c] = lap3<T>(sr[c * lmax + xm], r[c], sr[c * lmax + xp]);
+                    }
+                    bad |= !potential<T, C>(r, l, I.k, ph);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) sp[c * lmax + x] = ph[c];
+                }
+            }
+            __syncthreads();
+            // phase 3: force, friction, collision into LDS (all pulls of this
+            // step were taken before the first barrier)
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                const int x = tid + k * NT;
+                if (x < L) {
+                    const int xm = x == 0 ? L - 1 : x - 1, xp = x + 1 == L ? 0 : x + 1;
+                    T gx[C], lap[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const T rm = sr[c * lmax + xm], r0 = sr[c * lmax + x], rp = sr[c * lmax + xp];
+                        lap[c] = lap3<T>(rm, r0, rp);
+                        gx[c] = -rho[k][c] * grad3<T>(sp[c * lmax + xm], sp[c * lmax + xp]);
+                        if (I.k.force == 0) gx[c] += T(THETA) * grad3<T>(rm, rp);
+                    }
+                    if (tau1)
+                        collide_lds1<T, C, true>(p[k], rho[k], jx[k], gx, lap, I.k, sf, lmax, x);
+                    else
+                        collide_lds1<T, C, false>(p[k], rho[k], jx[k], gx, lap, I.k, sf, lmax, x);
+                }
+            }
+            if (bad) s_bad = 1;
+            __syncthreads();
+            if (s_bad) {
+                fail = t + 1;
+                break;
+            }
+        }
+        T* out = ((nsteps & 1) ? poolB : poolA) + I.offset;
+        for (int x = tid; x < L; x += NT)
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) {
+                T v[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) v[c] = sf[(i * C + c) * lmax + x];
+                store_site<T, C, false>(plane_base<T, C>(out, i, plane), x, v);
+            }
+        if (tid == 0) status[id] = fail;
+        __syncthreads();
+    }
+}
+
 // f = f^0(rho, u = 0) for every instance; one workgroup per instance.
 template <typename T, int C>
 __global__ void k_batch_init(const Instance<C>* __restrict__ inst, T* __restrict__ pool, const T* __restrict__ rho) {
@@ -217,6 +372,42 @@ __global__ void k_batch_rho(const Instance<C>* __restrict__ inst, const T* __res
     }
 }
 
+// D1Q3 versions of the two helpers above.
+template <typename T, int C>
+__global__ void k_batch_init1(const Instance<C>* __restrict__ inst, T* __restrict__ pool, const T* __restrict__ rho) {
+    const Instance<C>& I = inst[blockIdx.x];
+    const int n = I.g.nx;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        T p[C][Q1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) p[c][i] = T(0);
+            const T r = rho[I.rho_offset + (int64_t)c * n + x];
+            collide1<T, false>(p[c], r, T(1) / r, T(0), T(0), T(0), T(1), T(0), T(0));
+        }
+#pragma unroll
+        for (int i = 0; i < Q1; ++i) {
+            T v[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = p[c][i];
+            store_site<T, C, false>(plane_base<T, C>(pool + I.offset, i, I.g.plane), x, v);
+        }
+    }
+}
+
+template <typename T, int C>
+__global__ void k_batch_rho1(const Instance<C>* __restrict__ inst, const T* __restrict__ pool, T* __restrict__ rho) {
+    const Instance<C>& I = inst[blockIdx.x];
+    const int n = I.g.nx;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        T p[C][Q1];
+        pull1<T, C>(pool + I.offset, I.g.plane, x, wrapc(x - 1, n, 1), wrapc(x + 1, n, 1), p);
+#pragma unroll
+        for (int c = 0; c < C; ++c) rho[I.rho_offset + (int64_t)c * n + x] = density1<T>(p[c]);
+    }
+}
+
 }  // namespace vdwlb
 
 using namespace vdwlb;
@@ -224,6 +415,10 @@ using namespace vdwlb;
 struct vdwlb_batch {
     int n = 0, C = 0, dtype = 0, ny = 0;
     int taus = 0;  // 1: every instance has tau = 1, 2: none has, 0: mixed
+    int dim = 2;   // 1: D1Q3 instances resident in LDS (k_batch1)
+    int lmax = 0;  // D1Q3: largest instance, sites
+    int spt = 1;   // D1Q3: sites per thread
+    size_t lds1 = 0;  // D1Q3: dynamic LDS bytes per workgroup
     std::vector<int64_t> offset, rho_offset, sites;
     int64_t pool_elems = 0, rho_elems = 0;
     void* d_inst = nullptr;  // Instance<C>[n]
@@ -274,8 +469,38 @@ hipError_t launch_batch_ny(vdwlb_batch& b, void* A, void* B, int nsteps, int blo
     return hipErrorInvalidValue;
 }
 
+template <typename T, int C, int SPT, int TAUS>
+hipError_t launch_batch1_k(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, bool attr_only) {
+    auto kern = k_batch1<T, C, SPT, TAUS>;
+    if (attr_only)  // at creation, outside any stream capture
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)b.lds1);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(B1_THREADS), b.lds1, s, (const Instance<C>*)b.d_inst, b.d_order, b.n,
+                       (T*)A, (T*)B, nsteps, b.lmax, b.d_counter, b.d_status);
+    return hipGetLastError();
+}
+
+template <typename T, int C, int SPT>
+hipError_t launch_batch1_t(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, bool attr_only) {
+    if (b.taus == 1) return launch_batch1_k<T, C, SPT, 1>(b, A, B, nsteps, blocks, s, attr_only);
+    if (b.taus == 2) return launch_batch1_k<T, C, SPT, 2>(b, A, B, nsteps, blocks, s, attr_only);
+    return launch_batch1_k<T, C, SPT, 0>(b, A, B, nsteps, blocks, s, attr_only);
+}
+
+template <typename T, int C>
+hipError_t launch_batch1(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, bool attr_only) {
+    switch (b.spt) {
+        case 1: return launch_batch1_t<T, C, 1>(b, A, B, nsteps, blocks, s, attr_only);
+        case 2: return launch_batch1_t<T, C, 2>(b, A, B, nsteps, blocks, s, attr_only);
+        case 4: return launch_batch1_t<T, C, 4>(b, A, B, nsteps, blocks, s, attr_only);
+        case 8: return launch_batch1_t<T, C, 8>(b, A, B, nsteps, blocks, s, attr_only);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int C>
 hipError_t launch_batch_c(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s) {
+    if (b.dim == 1) return launch_batch1<T, C>(b, A, B, nsteps, blocks, s, false);
     // 1024-thread workgroups only for heights of 4 and 8 (wide strips of
     // 1- and 2-row lattices would exceed the LDS of a workgroup)
     if (b.threads == 1024 && b.ny >= 4) return launch_batch_ny<T, C, 1024>(b, A, B, nsteps, blocks, s);
@@ -303,6 +528,15 @@ hipError_t launch_batch(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks
 
 template <typename T, int C>
 hipError_t aux_c(vdwlb_batch& b, int what, void* pool, void* rho, hipStream_t s) {
+    if (b.dim == 1) {
+        if (what == 0)
+            hipLaunchKernelGGL((k_batch_init1<T, C>), dim3(b.n), dim3(256), 0, s, (const Instance<C>*)b.d_inst,
+                               (T*)pool, (const T*)rho);
+        else
+            hipLaunchKernelGGL((k_batch_rho1<T, C>), dim3(b.n), dim3(256), 0, s, (const Instance<C>*)b.d_inst,
+                               (const T*)pool, (T*)rho);
+        return hipGetLastError();
+    }
     if (what == 0)
         hipLaunchKernelGGL((k_batch_init<T, C>), dim3(b.n), dim3(256), 0, s, (const Instance<C>*)b.d_inst, (T*)pool,
                            (const T*)rho);
@@ -348,9 +582,17 @@ bool pool_aligned(const vdwlb_batch& b, const void* pool) {
 
 int device_blocks(const vdwlb_batch& b) {
     int dev = 0, cus = 256;
+    size_t lds_cu = 160 * 1024;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            cus = prop.multiProcessorCount;
+            if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_cu = prop.maxSharedMemoryPerMultiProcessor;
+        }
+    }
+    if (b.dim == 1) {  // as many resident workgroups as the LDS of a CU holds
+        const size_t per = std::max<size_t>(1, std::min<size_t>(8, lds_cu / std::max<size_t>(b.lds1 + 64, 1)));
+        return cus * (int)per;
     }
     const int per_cu = (b.threads == 1024 && b.ny >= 4) ? 1 : 4;
     return cus * per_cu;
@@ -374,9 +616,10 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
     std::vector<vdwlb_plan*> tmp(n, nullptr);
     std::vector<vdwlb_plan> plans;
     plans.reserve(n);
-    const int C = descs[0].ncomp, dtype = descs[0].dtype, ny = descs[0].ny;
+    const int C = descs[0].ncomp, dtype = descs[0].dtype, ny = descs[0].ny, dim = descs[0].dim;
     for (int k = 0; k < n; ++k) {
-        if (descs[k].ncomp != C || descs[k].dtype != dtype || descs[k].ny != ny) return VDWLB_E_INVALID_ARG;
+        if (descs[k].ncomp != C || descs[k].dtype != dtype || descs[k].ny != ny || descs[k].dim != dim)
+            return VDWLB_E_INVALID_ARG;
     }
     // Validate every description with the plan rules, on host data only.
     for (int k = 0; k < n; ++k) {
@@ -385,6 +628,20 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
         plans.push_back(plan_from_desc(descs[k]));
     }
     if (ny != 1 && ny != 2 && ny != 4 && ny != 8) return VDWLB_E_UNSUPPORTED;
+    // D1Q3: every instance must fit the LDS of one workgroup
+    int lmax = 0;
+    for (const vdwlb_plan& q : plans) lmax = std::max(lmax, q.nx);
+    const size_t lds1 = (size_t)5 * C * lmax * (dtype == VDWLB_F64 ? 8 : 4);
+    int spt = 1;
+    while (spt * 256 < lmax) spt *= 2;
+    if (dim == 1) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        size_t lds_wg = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lds_wg = prop.sharedMemPerBlock;
+        if (spt > 8 || lds1 + 64 > lds_wg) return VDWLB_E_UNSUPPORTED;
+    }
 
     vdwlb_batch* b = new (std::nothrow) vdwlb_batch();
     if (!b) return VDWLB_E_DEVICE;
@@ -392,6 +649,10 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
     b->C = C;
     b->dtype = dtype;
     b->ny = ny;
+    b->dim = dim;
+    b->lmax = lmax;
+    b->spt = spt;
+    b->lds1 = lds1;
     int n_tau1 = 0;
     for (const vdwlb_plan& q : plans) n_tau1 += q.tau == 1.0 ? 1 : 0;
     b->taus = n_tau1 == n ? 1 : (n_tau1 == 0 ? 2 : 0);
@@ -403,7 +664,7 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
         b->offset[k] = off;
         b->rho_offset[k] = roff;
         b->sites[k] = (int64_t)plans[k].nx * plans[k].ny;
-        off += (int64_t)Q * C * plans[k].plane;
+        off += (int64_t)(dim == 1 ? Q1 : Q) * C * plans[k].plane;
         roff += (int64_t)C * b->sites[k];
     }
     b->pool_elems = off;
@@ -427,6 +688,16 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
     if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->d_status, 0, sizeof(int) * n);
     if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 256);
+    if (e == hipSuccess && dim == 1)
+        e = b->dtype == VDWLB_F64
+                ? (C == 1   ? launch_batch1<double, 1>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                   : C == 2 ? launch_batch1<double, 2>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                   : C == 3 ? launch_batch1<double, 3>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                            : launch_batch1<double, 4>(*b, nullptr, nullptr, 0, 0, nullptr, true))
+                : (C == 1   ? launch_batch1<float, 1>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                   : C == 2 ? launch_batch1<float, 2>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                   : C == 3 ? launch_batch1<float, 3>(*b, nullptr, nullptr, 0, 0, nullptr, true)
+                            : launch_batch1<float, 4>(*b, nullptr, nullptr, 0, 0, nullptr, true));
     if (e != hipSuccess) {
         vdwlb_batch_destroy(b);
         return bfail(e, "batch device buffers");

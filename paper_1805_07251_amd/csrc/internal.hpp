@@ -38,9 +38,9 @@ struct Schedule {
 
 int schedule_count();
 Schedule schedule_at(int k);
-// Public schedule numbering: tile schedules in row-major XCD order, then the
-// same in vertical-band order.
-int public_schedule_count();
+// Public schedule numbering (D2Q9): tile schedules in row-major XCD order,
+// then the same in vertical-band order; D1Q3 plans have their own short list.
+int public_schedule_count(const vdwlb_plan& p);
 
 // Alignment the kernels need for a population buffer: the C components of a
 // site are one vector access when C is 2 or 4.

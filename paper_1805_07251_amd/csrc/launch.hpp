@@ -4,6 +4,7 @@
 #include "internal.hpp"
 #include "schedules.hpp"
 #include "sweep.hpp"
+#include "sweep1.hpp"
 
 namespace vdwlb {
 
@@ -66,8 +67,39 @@ hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hip
     }
 }
 
+inline Geometry1 make_geometry1(const vdwlb_plan& p, int tx) {
+    Geometry1 g;
+    g.nx = p.nx;
+    g.plane = p.plane;
+    g.wrap_general = p.nx < tx + 8 ? 1 : 0;
+    return g;
+}
+
+template <typename T, int C, int TX, bool NTS>
+hipError_t run_sweep1(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    const Geometry1 g = make_geometry1(p, TX);
+    const Coeffs<C> k = make_coeffs<C>(p);
+    const int tiles = (p.nx + TX - 1) / TX;
+    if (p.tau == 1.0)
+        hipLaunchKernelGGL((k_sweep1<T, C, TX, NTS, true>), dim3(tiles), dim3(TX), 0, s, (const T*)fin, (T*)fout, g,
+                           k, p.d_flag);
+    else
+        hipLaunchKernelGGL((k_sweep1<T, C, TX, NTS, false>), dim3(tiles), dim3(TX), 0, s, (const T*)fin, (T*)fout, g,
+                           k, p.d_flag);
+    return hipGetLastError();
+}
+
 template <typename T, int C>
 hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+    if (p.dim == 1) {
+        switch (p.sched) {
+#define VDWLB_SCHED1_CASE(i, tx, nt) \
+    case i: return run_sweep1<T, C, tx, nt>(p, fin, fout, s);
+            VDWLB_SCHEDULES1(VDWLB_SCHED1_CASE)
+#undef VDWLB_SCHED1_CASE
+            default: return hipErrorInvalidValue;
+        }
+    }
     return run_sweep_sched<T, C>(p, fin, fout, s);
 }
 

@@ -12,18 +12,22 @@ namespace vdwlb {
 int schedule_count() { return N_SCHEDULES; }
 Schedule schedule_at(int k) { return SCHEDULES[k]; }
 
-int public_schedule_count() { return 2 * N_SCHEDULES; }
+int public_schedule_count(const vdwlb_plan& p) { return p.dim == 1 ? N_SCHEDULES1 : 2 * N_SCHEDULES; }
 
 bool apply_public_schedule(vdwlb_plan& p, int k) {
-    if (k < 0 || k >= public_schedule_count()) return false;
+    if (k < 0 || k >= public_schedule_count(p)) return false;
+    if (p.dim == 1) {
+        p.sched = k;
+        p.map_mode = 0;
+        return true;
+    }
     p.sched = k % N_SCHEDULES;
     p.map_mode = k / N_SCHEDULES;
     return true;
 }
 
 int default_schedule(const vdwlb_plan& p) {
-    (void)p;
-    return 1;  // 64 x 8, non-temporal stores
+    return p.dim == 1 ? 0 : 1;  // 256 sites / 64 x 8 tiles, non-temporal stores
 }
 
 bool graphs_enabled() {
@@ -39,6 +43,12 @@ namespace {
 
 template <typename T, int C>
 hipError_t init_c(const vdwlb_plan& p, void* f, const void* rho, const void* mom, hipStream_t s) {
+    if (p.dim == 1) {
+        const Geometry1 g1 = make_geometry1(p, 256);
+        hipLaunchKernelGGL((k_init1<T, C>), dim3((p.nx + 255) / 256), dim3(256), 0, s, (T*)f, (const T*)rho,
+                           (const T*)mom, g1);
+        return hipGetLastError();
+    }
     const Geometry g = make_geometry(p, 64, 1);
     const int n = p.nx * p.ny;
     hipLaunchKernelGGL((k_init<T, C>), dim3((n + 255) / 256), dim3(256), 0, s, (T*)f, (const T*)rho,
@@ -48,6 +58,16 @@ hipError_t init_c(const vdwlb_plan& p, void* f, const void* rho, const void* mom
 
 template <typename T, int C>
 hipError_t moments_c(const vdwlb_plan& p, const void* f, void* rho, void* mom, void* mu, void* pr, hipStream_t s) {
+    if (p.dim == 1) {
+        const Geometry1 g1 = make_geometry1(p, 256);
+        const unsigned nb = (unsigned)((p.nx + 255) / 256);
+        hipLaunchKernelGGL((k_moments1<T, C>), dim3(nb), dim3(256), 0, s, (const T*)f, (T*)rho, (T*)mom, g1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || (!mu && !pr)) return e;
+        hipLaunchKernelGGL((k_mu_p1<T, C>), dim3(nb), dim3(256), 0, s, (const T*)rho, (T*)mu, (T*)pr, g1,
+                           make_coeffs<C>(p), p.d_flag);
+        return hipGetLastError();
+    }
     const Geometry g = make_geometry(p, 64, 1);
     const int n = p.nx * p.ny;
     hipLaunchKernelGGL((k_moments<T, C>), dim3((n + 255) / 256), dim3(256), 0, s, (const T*)f, (T*)rho, (T*)mom,

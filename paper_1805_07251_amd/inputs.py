@@ -55,6 +55,7 @@ class Workload:
     force: int = 0
     dtype: str = "f64"
     name: str = ""
+    dim: int = 2  # 2: D2Q9, 1: D1Q3 (ny = 1)
 
     def __post_init__(self):
         C = self.b.shape[0]
@@ -147,11 +148,12 @@ def one_fluid_a(xbar: float, nu: float) -> float:
 
 
 def slab_instance(L: int, ny: int, t: float, xbar: float, nu: float, rho_gas: float, rho_liq: float,
-                  width: float = 2.0) -> Workload:
+                  width: float = 2.0, dim: int = 2) -> Workload:
     """One quasi-1-D lattice: a liquid slab between x = L/4 and 3L/4 with tanh
     edges of the given width (Sec. V initialises with tanh profiles), bulk
     total densities rho_liq / rho_gas supplied by the caller, uniform mole
-    fraction xbar, y-uniform.  gamma_mu is half the value of the rule
+    fraction xbar, y-uniform (dim = 1: a D1Q3 line, ny = 1).  gamma_mu is
+    half the value of the rule
     c_s^2 = 1 - 4 kappa rho_l gamma_mu (Eq. kappaGammaMuRelation): Sec. VI.A
     lowers gamma_mu by factors of 2 to 10 for runs that are unstable at the
     rule's value."""
@@ -163,24 +165,37 @@ def slab_instance(L: int, ny: int, t: float, xbar: float, nu: float, rho_gas: fl
     rho[0] = (xbar * tot)[None, :]
     rho[1] = ((1.0 - xbar) * tot)[None, :]
     gamma = 0.5 * (1.0 - 1.0 / 3.0) / (4.0 * KAPPA * rho_liq)
-    return Workload(L, ny, t * KT_CRIT, a, b, kappa_matrix(a), rho, gamma_mu=gamma, name=f"slab L={L}")
+    return Workload(L, ny, t * KT_CRIT, a, b, kappa_matrix(a), rho, gamma_mu=gamma, name=f"slab L={L}", dim=dim)
 
 
-def batch_slabs(maxwell, seed: int = 0, n: int = 1024, ny: int = 4, idx=None, lmax=None):
+def batch_slabs(maxwell, seed: int = 0, n: int = 1024, ny: int = 4, idx=None, lmax=None, dim: int = 2):
     """The batched phase-diagram workload: n quasi-1-D L x ny lattices with L
     uniform in [128, 1024], kT in [0.6, 1.0] kT_crit, mole fraction in
     [0.05, 0.95] and a12/a11 in [0.6, 1.2], each initialised with a liquid
     slab.  maxwell(a, b, kT) -> (rho_gas, rho_liquid) or None supplies the
     bulk densities of the one-fluid approximation of each mixture (uniform
-    density 0.5 / b when it is above its critical temperature)."""
+    density 0.5 / b when it is above its critical temperature).  dim = 1
+    gives the same draws as D1Q3 lines (ny is then 1)."""
     d = batch_draws(seed, n)
     out = []
     for k in (range(n) if idx is None else idx):
         L = int(d.L[k]) if lmax is None else int(min(d.L[k], lmax))
         m = maxwell(one_fluid_a(d.xbar[k], d.nu[k]), B1, d.t[k] * KT_CRIT)
         rg, rl = m if m else (0.5 / B1, 0.5 / B1)
-        out.append(slab_instance(L, ny, d.t[k], d.xbar[k], d.nu[k], rg, rl))
+        out.append(slab_instance(L, 1 if dim == 1 else ny, d.t[k], d.xbar[k], d.nu[k], rg, rl, dim=dim))
     return out
+
+
+def line_spinodal(seed: int = 0, L: int = 512, C: int = 2, nu: float = 0.9, dtype: str = "f64") -> Workload:
+    """The spinodal_small parameters on a D1Q3 line of L sites (Sec. V's own
+    lattice): C components split equally at packing fraction 0.5, +-1 %
+    multiplicative noise."""
+    a = np.full((C, C), nu * A11)
+    np.fill_diagonal(a, A11)
+    b = np.full(C, B1)
+    rng = np.random.default_rng(seed)
+    rho = _noise_field(rng, np.full(C, 0.5 / (B1 * C)), 1, L)
+    return Workload(L, 1, 0.8 * KT_CRIT, a, b, kappa_matrix(a), rho, dtype=dtype, name=f"line L={L} C={C}", dim=1)
 
 
 def adjoint_case(seed: int = 0, n: int = 256):

@@ -1,4 +1,5 @@
-"""Python front end of the plain sweep: one periodic D2Q9 lattice on the GPU.
+"""Python front end of the plain sweep: one periodic D2Q9 (or D1Q3) lattice on
+the GPU.
 
 torch supplies device memory and the stream; every lattice operation is a
 call into libvdwlb.so.
@@ -31,17 +32,20 @@ def _stream_ptr(stream=None) -> int:
 class Plan:
     """Owns a vdwlb_plan handle."""
 
-    def __init__(self, nx, ny, kT, a, b, kappa, tau=1.0, gamma_mu=1.0, lam=None, dtype="f64", force=V.FORCE_LOG):
+    def __init__(self, nx, ny, kT, a, b, kappa, tau=1.0, gamma_mu=1.0, lam=None, dtype="f64", force=V.FORCE_LOG,
+                 dim=2):
         self.a = np.ascontiguousarray(a, dtype=np.float64)
         self.b = np.ascontiguousarray(b, dtype=np.float64)
         self.kappa = np.ascontiguousarray(kappa, dtype=np.float64)
         C = self.b.shape[0]
         self.lam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         self.C, self.nx, self.ny = C, int(nx), int(ny)
+        self.dim = int(dim)
+        self.Q = 3 if self.dim == 1 else 9
         self.dtype = _dtype_code(dtype)
         self.torch_dtype = _TORCH_DT[self.dtype]
         ptr = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if arr is not None else None
-        d = V.Desc(2, self.nx, self.ny, C, self.dtype, force, float(kT), float(tau), float(gamma_mu),
+        d = V.Desc(self.dim, self.nx, self.ny, C, self.dtype, force, float(kT), float(tau), float(gamma_mu),
                    ptr(self.a), ptr(self.b), ptr(self.kappa), ptr(self.lam))
         h = ctypes.c_void_p()
         V.check(V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)), "vdwlb_plan_create")
@@ -57,15 +61,15 @@ class Plan:
 
     @property
     def state_elems(self) -> int:
-        return 9 * self.C * self.plane
+        return self.Q * self.C * self.plane
 
 
 class Lattice:
     """A lattice with its two population buffers on the current CUDA device."""
 
     def __init__(self, nx, ny, kT, a, b, kappa, tau=1.0, gamma_mu=1.0, lam=None, dtype="f64", force=V.FORCE_LOG,
-                 device="cuda"):
-        self.plan = Plan(nx, ny, kT, a, b, kappa, tau, gamma_mu, lam, dtype, force)
+                 device="cuda", dim=2):
+        self.plan = Plan(nx, ny, kT, a, b, kappa, tau, gamma_mu, lam, dtype, force, dim)
         self.device = torch.device(device)
         n = self.plan.state_elems
         self.buf = [torch.empty(n, dtype=self.plan.torch_dtype, device=self.device) for _ in range(2)]
@@ -74,7 +78,8 @@ class Lattice:
 
     @classmethod
     def from_workload(cls, w, dtype=None, device="cuda"):
-        return cls(w.nx, w.ny, w.kT, w.a, w.b, w.kappa, w.tau, w.gamma_mu, w.lam, dtype or w.dtype, w.force, device)
+        return cls(w.nx, w.ny, w.kT, w.a, w.b, w.kappa, w.tau, w.gamma_mu, w.lam, dtype or w.dtype, w.force, device,
+                   getattr(w, "dim", 2))
 
     @property
     def C(self):
@@ -113,20 +118,24 @@ class Lattice:
         self.steps_done += int(n)
 
     @property
+    def Q(self):
+        return self.plan.Q
+
+    @property
     def state(self) -> torch.Tensor:
-        """The current population buffer in its storage layout [9, plane, C]
+        """The current population buffer in its storage layout [Q, plane, C]
         (velocity planes of sites, the components of a site adjacent)."""
-        return self.buf[self.cur].view(9, self.plan.plane, self.C)
+        return self.buf[self.cur].view(self.Q, self.plan.plane, self.C)
 
     def state_sites(self) -> torch.Tensor:
-        """Populations as [C, 9, ny, nx] (a copy without the plane padding)."""
+        """Populations as [C, Q, ny, nx] (a copy without the plane padding)."""
         n = self.nx * self.ny
-        return self.state[:, :n, :].permute(2, 0, 1).reshape(self.C, 9, self.ny, self.nx).clone()
+        return self.state[:, :n, :].permute(2, 0, 1).reshape(self.C, self.Q, self.ny, self.nx).clone()
 
     def set_state(self, f) -> None:
-        """Load populations given as [C, 9, ny, nx] into the current buffer."""
+        """Load populations given as [C, Q, ny, nx] into the current buffer."""
         n = self.nx * self.ny
-        t = self._field(f, (self.C, 9, self.ny, self.nx)).reshape(self.C, 9, n)
+        t = self._field(f, (self.C, self.Q, self.ny, self.nx)).reshape(self.C, self.Q, n)
         self.state[:, :n, :].copy_(t.permute(1, 2, 0))
 
     def moments(self, want_mu=True, want_p=True, stream=None):

@@ -86,9 +86,14 @@ def test_null_arguments():
     assert V.lib().vdwlb_plan_destroy(None) == V.OK
 
 
-def test_unsupported_dimension():
+def test_dimension_rules():
+    """D1Q3 plans (dim = 1) must be nx x 1; other dimensions are invalid.
+    Both are decided on host data, before any device call."""
     import ctypes
 
-    d, keep = _desc(dim=1)
     h = ctypes.c_void_p()
-    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_UNSUPPORTED
+    d, keep = _desc(dim=1)
+    assert d.ny != 1
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
+    d, keep = _desc(dim=3)
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG

@@ -1,0 +1,373 @@
+"""GPU tests of the D1Q3 path (the paper's own 1-D scheme, Sec. V): the plain
+sweep on lines (plans with dim = 1) and the batched form whose instances stay
+resident in LDS, against the CPU oracle's D1Q3 and against each other.
+
+The last tests are the paper's verification in small: a flat liquid slab must
+relax to the thermodynamic coexistence of the bulk free energy (Sec. VI.A
+compares the lattice with the common-tangent construction), checked with the
+oracle's separate thermodynamic solver.
+"""
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+from paper_1805_07251_amd import inputs as I
+
+from ._util import oracle_run, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import batch, lattice
+
+    return batch, lattice
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_line(lattice, w, nsteps, dtype=None, sched=None):
+    lat = lattice.Lattice.from_workload(w, dtype=dtype)
+    if sched is not None:
+        lat.set_schedule(sched)
+    lat.init(w.rho)
+    if nsteps:
+        lat.run(nsteps)
+    return lat
+
+
+def test_line_f64_1000_steps(gpu, orc):
+    """Two components on 512 sites, 1000 steps: densities within 1e-12 of
+    the oracle (the same bound as the D2Q9 parity runs)."""
+    _, lattice = gpu
+    w = I.line_spinodal(0, L=512)
+    ref, st = oracle_run(orc, w, 1000, dim=1)
+    assert st == 0
+    lat = gpu_line(lattice, w, 1000)
+    assert lat.status() == 0
+    rho, mom, mu, p = lat.moments()
+    r_rho, r_mom, r_mu, r_p, _ = ref.moments()
+    assert rel_err(np_(rho), r_rho) <= 1e-12
+    assert rel_err(np_(mom)[:, 0], r_mom[:, 0]) <= 1e-10
+    assert np.all(np_(mom)[:, 1] == 0)
+    assert np.abs(np_(mu) - r_mu).max() <= 1e-11 * np.abs(r_mu).max()
+    assert np.abs(np_(p) - r_p).max() <= 1e-11 * np.abs(r_p).max()
+
+
+def test_line_f32(gpu, orc):
+    _, lattice = gpu
+    w = I.line_spinodal(1, L=300, dtype="f32")
+    ref, _ = oracle_run(orc, w, 500, dim=1)
+    lat = gpu_line(lattice, w, 500)
+    assert rel_err(np_(lat.moments(want_mu=False, want_p=False)[0]), ref.moments()[0]) <= 1e-4
+
+
+@pytest.mark.parametrize("sched", range(4))
+def test_every_schedule_ragged(gpu, orc, sched):
+    """Full populations after 3 steps on 1000 sites (no tile width divides
+    it) for every D1Q3 schedule."""
+    _, lattice = gpu
+    w = I.line_spinodal(2, L=1000)
+    w.rho = np.random.default_rng(5).uniform(2.5, 2.75, (2, 1, 1000))
+    ref, _ = oracle_run(orc, w, 3, dim=1)
+    lat = gpu_line(lattice, w, 3, sched=sched)
+    assert lat.schedule_count() == 4
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-14)
+
+
+def test_schedules_bitwise_identical(gpu):
+    _, lattice = gpu
+    w = I.line_spinodal(3, L=3000)
+    outs = [np_(gpu_line(lattice, w, 25, sched=s).state_sites()) for s in range(4)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("nx", [1, 2, 3, 5, 9, 260])
+def test_short_lines(gpu, orc, nx):
+    """Lines shorter than the stencil reach wrap several times."""
+    _, lattice = gpu
+    w = I.line_spinodal(0, L=nx)
+    w.rho = np.random.default_rng(nx).uniform(2.55, 2.7, (2, 1, nx))
+    ref, _ = oracle_run(orc, w, 12, dim=1)
+    lat = gpu_line(lattice, w, 12)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("C", [1, 3, 4])
+def test_component_counts(gpu, orc, C):
+    _, lattice = gpu
+    w = I.line_spinodal(4, L=200, C=C)
+    w.lam = np.random.default_rng(9).uniform(0.5, 2.0, (C, C))
+    w.lam = 0.5 * (w.lam + w.lam.T)
+    ref, st = oracle_run(orc, w, 100, dim=1)
+    assert st == 0
+    lat = gpu_line(lattice, w, 100)
+    assert rel_err(np_(lat.moments(want_mu=False, want_p=False)[0]), ref.moments()[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("force,tau", [(1, 1.0), (0, 0.8), (1, 1.3)])
+def test_nid_and_tau(gpu, orc, force, tau):
+    _, lattice = gpu
+    w = I.line_spinodal(5, L=128)
+    w.force, w.tau = force, tau
+    ref, st = oracle_run(orc, w, 200, dim=1)
+    assert st == 0
+    lat = gpu_line(lattice, w, 200)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-12)
+
+
+def test_initial_velocity(gpu, orc):
+    _, lattice = gpu
+    w = I.line_spinodal(6, L=64)
+    mom = np.zeros((2, 2, 1, 64))
+    mom[:, 0] = 0.05 * np.sin(2 * np.pi * np.arange(64) / 64) * w.rho
+    ref = orc.Lattice(orc.Params(w.kT, w.a, w.b, w.kappa, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam), 1, 64, 1)
+    ref.init(w.rho, mom)
+    ref.run(20)
+    lat = lattice.Lattice.from_workload(w)
+    lat.init(w.rho, mom)
+    lat.run(20)
+    np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-13)
+
+
+def test_unphysical_flagged(gpu):
+    from paper_1805_07251_amd import vdwlb as V
+
+    _, lattice = gpu
+    w = I.line_spinodal(0, L=64)
+    w.rho = w.rho.copy()
+    w.rho[:, :, 20:30] = 12.0  # eta > 1
+    lat = gpu_line(lattice, w, 2)
+    assert lat.status() == V.E_UNPHYSICAL
+
+
+def test_d1q3_plan_rules(gpu):
+    """D1Q3 plans need ny = 1; the adjoint is a D2Q9 feature."""
+    from paper_1805_07251_amd import vdwlb as V
+
+    _, lattice = gpu
+    w = I.line_spinodal(0, L=32)
+    with pytest.raises(V.VdwlbError) as ei:
+        lattice.Lattice(32, 2, w.kT, w.a, w.b, w.kappa, dim=1)
+    assert ei.value.status == V.E_INVALID_ARG
+    lat = lattice.Lattice.from_workload(w)
+    assert int(V.lib().vdwlb_adjoint_segment(lat.plan.handle, lat.buf[0].data_ptr(), 1, lat.buf[1].data_ptr(),
+                                             lat.buf[1].data_ptr(), lat.buf[1].data_ptr(), None)) == V.E_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ batch
+def line_slabs(seed, idx, lmax=None):
+    return I.batch_slabs(T.maxwell_single, seed, idx=list(idx), lmax=lmax, dim=1)
+
+
+def plain_line_state(lattice, w, nsteps):
+    return np_(gpu_line(lattice, w, nsteps).state_sites())
+
+
+def batch_run(batch, ws, chunks, dtype="f64"):
+    b = batch.Batch(ws, dtype=dtype)
+    b.init([w.rho for w in ws])
+    for n in chunks:
+        b.run(n)
+    return b
+
+
+@pytest.mark.parametrize("lengths", [[1, 2, 7, 64, 255, 256], [257, 511, 700, 1024], [1025, 1500, 2040]])
+def test_batch_matches_plain_bitwise(gpu, lengths):
+    """Resident instances of every size class (1, 2, 4 and 8 sites per
+    thread) equal their plain D1Q3 runs bit for bit."""
+    batch, lattice = gpu
+    ws = line_slabs(7, range(len(lengths)))
+    for w, L in zip(ws, lengths):
+        w.nx = L
+        w.rho = np.random.default_rng(L).uniform(2.0, 3.5, (2, 1, L))
+    b = batch_run(batch, ws, [41])
+    assert np.all(b.status() == 0)
+    for k, w in enumerate(ws):
+        assert np.array_equal(np_(b.state(k)), plain_line_state(lattice, w, 41)), k
+
+
+def test_batch_against_oracle(gpu, orc):
+    batch, _ = gpu
+    ws = line_slabs(8, range(4), lmax=200)
+    b = batch_run(batch, ws, [30, 30])
+    assert np.all(b.status() == 0)
+    rho = [np_(r) for r in b.densities()]
+    for k, w in enumerate(ws):
+        ref, st = oracle_run(orc, w, 60, dim=1)
+        assert st == 0
+        assert rel_err(rho[k], ref.moments()[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("taus", ["mixed", "none"])
+def test_batch_tau_mix(gpu, taus):
+    batch, lattice = gpu
+    ws = line_slabs(9, range(5), lmax=600)
+    for k, w in enumerate(ws):
+        if taus == "none" or k % 2:
+            w.tau = 0.75 + 0.1 * k
+    b = batch_run(batch, ws, [33])
+    for k, w in enumerate(ws):
+        assert b.status()[k] == 0
+        assert np.array_equal(np_(b.state(k)), plain_line_state(lattice, w, 33)), k
+
+
+def test_batch_f32_and_unphysical(gpu):
+    batch, lattice = gpu
+    ws = line_slabs(10, range(4), lmax=400)
+    ws[2].rho = ws[2].rho.copy()
+    ws[2].rho[:, :, 5:15] = 12.0
+    b = batch_run(batch, ws, [20], dtype="f32")
+    st = b.status()
+    assert st[2] == 1 and st[0] == st[1] == st[3] == 0
+    for k in (0, 1, 3):
+        lat = gpu_line(lattice, ws[k], 20, dtype="f32")
+        assert np.array_equal(np_(b.state(k)), np_(lat.state_sites())), k
+
+
+def test_batch_too_long_rejected(gpu):
+    from paper_1805_07251_amd import vdwlb as V
+
+    batch, _ = gpu
+    ws = line_slabs(11, range(2))
+    ws[0].nx = 5000
+    ws[0].rho = np.full((2, 1, 5000), 2.6)
+    with pytest.raises(V.VdwlbError) as ei:
+        batch.Batch(ws)
+    assert ei.value.status == V.E_UNSUPPORTED
+
+
+# ------------------------------------------------------- coexistence
+def slab_profile(L, rg, rl, w=2.0):
+    x = np.arange(L) + 0.5
+    return rg + (rl - rg) * 0.5 * (np.tanh((x - L / 4) / w) - np.tanh((x - 3 * L / 4) / w))
+
+
+def window_mean(r, x, half=2):
+    """Mean over 2 half + 1 sites around x (periodic): the converged slabs
+    carry a period-2 ripple of ~1e-8 relative (the central difference leaves
+    that mode undamped), which the mean suppresses."""
+    L = r.shape[-1]
+    return r[..., (x + np.arange(-half, half + 1)) % L].mean(-1)
+
+
+def test_single_component_coexistence_curve(gpu):
+    """Six temperatures from 0.6 to 0.85 kT_crit in one batch, each a
+    128-site line started 10 % off the coexistence densities: after 80,000
+    steps (converged) the bulk densities equal the Maxwell values (equal
+    chemical potential and pressure, Sec. II) to 1e-6, the lattice-pinning
+    shift of these kappa = 0.4 interfaces (largest at the lowest temperature,
+    where the interface is sharpest; closer to the critical point the
+    interfaces widen and a 128-site line no longer has a bulk region at this
+    accuracy)."""
+    batch, _ = gpu
+    from paper_1805_07251_amd.inputs import A11, B1, KT_CRIT, Workload
+
+    ts = np.linspace(0.6, 0.85, 6)
+    ws, ref = [], []
+    kap = 0.4
+    for t in ts:
+        rg, rl = T.maxwell_single(A11, B1, t * KT_CRIT)
+        gam = T.gamma_from_width_rule(kap, rl)
+        prof = slab_profile(128, 1.1 * rg, 0.97 * rl)
+        ws.append(Workload(128, 1, t * KT_CRIT, np.array([[A11]]), np.array([B1]), np.array([[kap]]),
+                           prof[None, None, :], gamma_mu=gam, dim=1))
+        ref.append((rg, rl))
+    b = batch_run(batch, ws, [70000])
+    before = [np_(r)[0, 0].copy() for r in b.densities()]
+    b.run(10000)
+    assert np.all(b.status() == 0)
+    for k, r in enumerate(b.densities()):
+        r = np_(r)[0, 0]
+        rg, rl = ref[k]
+        liq, gas = window_mean(r, 64), window_mean(r, 0)
+        assert abs(liq - window_mean(before[k], 64)) < 1e-9 * rl  # converged
+        assert abs(liq - rl) < 1e-6 * rl, (ts[k], liq, rl)
+        assert abs(gas - rg) < 1e-6 * rg, (ts[k], gas, rg)
+
+
+def test_two_identical_components_coexistence(gpu):
+    """Two identical components (nu = 1, Sec. VI.A, Fig.
+    graphTwoIdenticalComponents) at four temperatures: both phases keep the
+    equal composition and their total densities are the one-component
+    Maxwell values, to 1e-5 (the bound of the oracle's own D2Q9 test of this
+    case) with kappa = 0.4 per component."""
+    batch, _ = gpu
+    from paper_1805_07251_amd.inputs import A11, B1, KT_CRIT, Workload
+
+    ts = np.linspace(0.7, 0.85, 4)
+    ws, ref = [], []
+    kap = 0.4
+    for t in ts:
+        rg, rl = T.maxwell_single(A11, B1, t * KT_CRIT)
+        gam = T.gamma_from_width_rule(2 * kap, rl)
+        prof = slab_profile(128, 1.1 * rg, 0.97 * rl)
+        ws.append(Workload(128, 1, t * KT_CRIT, np.full((2, 2), A11), np.array([B1, B1]), np.full((2, 2), kap),
+                           np.stack([0.5 * prof, 0.5 * prof])[:, None, :], gamma_mu=gam, dim=1))
+        ref.append((rg, rl))
+    b = batch_run(batch, ws, [200000])
+    assert np.all(b.status() == 0)
+    for k, r in enumerate(b.densities()):
+        r = np_(r)[:, 0]
+        np.testing.assert_allclose(r[0], r[1], rtol=1e-12)
+        tot = r.sum(0)
+        rg, rl = ref[k]
+        assert abs(window_mean(tot, 64) - rl) < 1e-5 * rl, (ts[k], window_mean(tot, 64), rl)
+        assert abs(window_mean(tot, 0) - rg) < 1e-5 * rg, (ts[k], window_mean(tot, 0), rg)
+
+
+def test_mixture_slabs_equal_chemical_potentials(gpu):
+    """Two-component slabs of the batched phase-diagram draws (kT, mole
+    fraction and a12 drawn as for the D2Q9 batch; 128 sites, kappa = 0.2),
+    400,000 steps.  Wherever the final state is steady and both sample points
+    (slab centre, far edge) lie in flat bulk regions, the two bulk states have
+    equal chemical potentials by the bulk thermodynamics of Sec. II (the
+    lattice equilibrium is uniform mu, Sec. VI.A).  Their pressures agree only
+    up to the lattice pinning of these sharp interfaces: a slab started from
+    one-fluid densities can stop on the lattice before the bulk pressures
+    meet, so the mismatch is reported, not asserted (the interface-width
+    tuning that removes it is a separate tool)."""
+    batch, _ = gpu
+    ws = line_slabs(12, range(48), lmax=128)
+    for w in ws:
+        w.kappa = I.kappa_matrix(w.a, 0.2)
+        w.gamma_mu = 0.5 * (1 - 1 / 3) / (4 * 0.2 * w.rho.sum(0).max())
+    b = batch_run(batch, ws, [300000])
+    before = [np_(r)[:, 0].copy() for r in b.densities()]
+    b.run(100000)
+    st = b.status()
+    checked = 0
+    worst_mu = worst_p = 0.0
+    for k, r in enumerate(b.densities()):
+        if st[k] != 0:
+            continue
+        r = np_(r)[:, 0]  # [C, L]
+        L = r.shape[1]
+        if np.abs(r - before[k]).max() > 1e-8 * r.max():  # still moving
+            continue
+        flat = lambda x: np.ptp(r[:, (x + np.arange(-8, 9)) % L], axis=1).max() < 1e-8 * r.max()
+        if not (flat(0) and flat(L // 2)):
+            continue
+        liq, gas = window_mean(r, L // 2), window_mean(r, 0)
+        if np.abs(liq - gas).max() < 0.5:  # one phase
+            continue
+        w = ws[k]
+        mu_l = T.chemical_potential(liq, w.kT, w.a, w.b)
+        mu_g = T.chemical_potential(gas, w.kT, w.a, w.b)
+        p_l = T.pressure(liq, w.kT, w.a, w.b)
+        p_g = T.pressure(gas, w.kT, w.a, w.b)
+        worst_mu = max(worst_mu, np.abs(mu_l - mu_g).max() / np.abs(mu_l).max())
+        worst_p = max(worst_p, abs(p_l - p_g) / abs(p_l))
+        checked += 1
+    print(f"steady two-phase bulk instances {checked}, max rel |dmu| {worst_mu:.2e}, "
+          f"max rel |dp| {worst_p:.2e} (lattice pinning)")
+    assert (st == 0).mean() > 0.9
+    assert checked >= 8
+    assert worst_mu <= 1e-7
