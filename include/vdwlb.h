@@ -11,17 +11,22 @@
  * mean-field force from its gradient (Eqs. forceMuLog / forceMuId), the
  * inter-component friction with implicit true velocities (Eq. forceFriction),
  * and the forced BGK collision (Eqs. BGKcollisionOperator, feq, with the
- * second-moment correction of Eq. forceCorrectionsPsi).
+ * second-moment correction of Eq. forceCorrectionsPsi).  Plans with dim = 1
+ * run the paper's own D1Q3 scheme on nx x 1 lines (Sec. V: 3-point
+ * stencils, the D1Q3 interaction function and the explicit update with
+ * F_0 = -S, F_+- = (S +- G)/2).
  *
  * Conventions fixed by this interface
- *  - Populations are stored as nine velocity planes of sites with the C
- *    components of a site adjacent: f_i^c at site s = y*nx + x (x fastest) is
- *    element (i * P + s) * C + c, P = vdwlb_plane_elems() sites per plane.
+ *  - Populations are stored as Q velocity planes of sites (Q = 9 for D2Q9,
+ *    3 for D1Q3) with the C components of a site adjacent: f_i^c at site
+ *    s = y*nx + x (x fastest) is element (i * P + s) * C + c,
+ *    P = vdwlb_plane_elems() sites per plane.
  *    One site's populations of all components are then a single vector
  *    access.  Population buffers must be aligned to C * sizeof(dtype) bytes
  *    (hipMalloc memory always is); misaligned pointers return
- *    VDWLB_E_INVALID_ARG.  The velocity order is v_0 = (0,0),
- *    v_1..4 = (1,0),(0,1),(-1,0),(0,-1), v_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
+ *    VDWLB_E_INVALID_ARG.  The D2Q9 velocity order is v_0 = (0,0),
+ *    v_1..4 = (1,0),(0,1),(-1,0),(0,-1), v_5..8 = (1,1),(-1,1),(-1,-1),(1,-1);
+ *    the D1Q3 order is v_0 = 0, v_1 = +1, v_2 = -1.
  *  - A stored state is post-collision, pre-stream; a step reads f_i(x - v_i)
  *    from one buffer and writes the new state to the other (ping-pong).
  *  - Physical force convention: momentum of component c gains
@@ -64,7 +69,8 @@ enum { VDWLB_F64 = 0, VDWLB_F32 = 1 };             /* storage and arithmetic pre
 enum { VDWLB_FORCE_LOG = 0, VDWLB_FORCE_NID = 1 }; /* Eq. forceMuLog / Eq. forceMuId */
 
 /* Description of one lattice and its parameters (Secs. II, III, V).
- *   dim      2 (D2Q9).  1 (D1Q3) is reserved and returns VDWLB_E_UNSUPPORTED.
+ *   dim      2 (D2Q9) or 1 (D1Q3, Sec. V; ny must be 1).  Moments of a D1Q3
+ *            plan report a zero y momentum.
  *   nx, ny   periodic extents, >= 1 each (small extents wrap several times),
  *            nx * ny <= 2^28 and one plane of a population buffer below
  *            2^32 bytes (plane_elems * C * sizeof(dtype)).
@@ -183,12 +189,18 @@ vdwlb_status vdwlb_copy(void* dst, const void* src, size_t nbytes, void* stream)
  * interface simulations with their own parameters, Sec. VI.A).
  *
  * Every instance has its own vdwlb_desc (size, kT, a, b, kappa, lambda, tau,
- * gamma_mu, force); all share ncomp, dtype and the lattice height ny, which
- * must be 1, 2, 4 or 8 (quasi-1-D lattices; other heights return
- * VDWLB_E_UNSUPPORTED).  The states of all instances live in one pool buffer
- * (two pools for ping-pong): instance k occupies the 9 * C * plane_k elements
- * starting at vdwlb_batch_offset(k), laid out as a plain state.  Density
- * arrays are packed the same way: instance k's [C][ny][nx] block starts at
+ * gamma_mu, force); all share dim, ncomp, dtype and the lattice height ny.
+ *  - D2Q9 (dim = 2): ny must be 1, 2, 4 or 8 (quasi-1-D lattices; other
+ *    heights return VDWLB_E_UNSUPPORTED); each workgroup streams its instance
+ *    through L2/MALL in full-height strips.
+ *  - D1Q3 (dim = 1): each workgroup holds its whole instance in LDS for all
+ *    steps of a run (5 C nx sizeof(dtype) bytes, which must fit one
+ *    workgroup's LDS, and nx <= 2048; otherwise VDWLB_E_UNSUPPORTED); the
+ *    launch shape below is chosen by the library.
+ * The states of all instances live in one pool buffer (two pools for
+ * ping-pong): instance k occupies the Q * C * plane_k elements starting at
+ * vdwlb_batch_offset(k), laid out as a plain state.  Density arrays are
+ * packed the same way: instance k's [C][ny][nx] block starts at
  * vdwlb_batch_density_offset(k).
  * ------------------------------------------------------------------------ */
 typedef struct vdwlb_batch vdwlb_batch;
@@ -209,8 +221,9 @@ int64_t vdwlb_batch_offset(const vdwlb_batch* batch, int32_t k);
 /* Element offset of instance k's density block in packed density arrays. */
 int64_t vdwlb_batch_density_offset(const vdwlb_batch* batch, int32_t k);
 
-/* Launch shape of the persistent kernel: threads per workgroup (256 or 1024)
- * and resident workgroups (0 = as many as the device holds, capped at n). */
+/* Launch shape of the persistent kernel: threads per workgroup (256 or 1024;
+ * D2Q9 batches only) and resident workgroups (0 = as many as the device
+ * holds, capped at n). */
 vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* batch, int32_t threads, int32_t blocks);
 
 /* pool = f^0(rho, u = 0) for every instance; rho is the packed density array
@@ -238,8 +251,8 @@ vdwlb_status vdwlb_batch_status(vdwlb_batch* batch, int32_t* per_instance, void*
 /* ------------------------------------------------------------------------
  * Adjoint (reverse-mode derivative) of the sweep, for gradients of a loss on
  * the final densities with respect to the free-energy parameters of Sec. II
- * (kT, a^{cc'}, b^c, kappa^{cc'}) through many steps.  FP64 plans with C = 1
- * or 2 only (others return VDWLB_E_UNSUPPORTED).
+ * (kT, a^{cc'}, b^c, kappa^{cc'}) through many steps.  FP64 D2Q9 plans with
+ * C = 1 or 2 only (others return VDWLB_E_UNSUPPORTED).
  *
  * Parameter cotangent vector (double, device), vdwlb_adjoint_param_count()
  * entries: kT, then a^{cd} for c <= d (row-major upper triangle), then b^c,
