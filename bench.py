@@ -10,6 +10,9 @@ value      MLUPS x components (million site updates per second times C), inputs
 roofline   the sweep kernel against the 8 TB/s HBM peak, with algorithmic bytes
            2 * 9 * C * sizeof(real) per site update.
 cpu_baseline  the CPU oracle on the host, a bounded sample of the same workload.
+extra      FP32 and 4-component sweeps, the batched phase-diagram workload in
+           D2Q9 (strips through L2/MALL) and D1Q3 (instances resident in LDS),
+           a 2^24-site D1Q3 line, and the adjoint against the plain forward.
 """
 from __future__ import annotations
 
@@ -71,7 +74,7 @@ def sweep_line(w, dtype, steps, warmup, schedule=-1):
     st = lat.status()
     sites = w.nx * w.ny
     real = 8 if dtype == "f64" else 4
-    bytes_per_site = 2 * 9 * w.C * real
+    bytes_per_site = 2 * (3 if getattr(w, "dim", 2) == 1 else 9) * w.C * real
     us = secs / steps * 1e6
     return {
         "workload": w.name,
@@ -212,6 +215,69 @@ def batch_leg(seed, steps, warmup):
     }
 
 
+def batch_d1q3_leg(seed, steps):
+    """The same phase-diagram draws as D1Q3 lines (the paper's own lattice):
+    1024 lines, L in [128, 1024], every instance resident in LDS for the
+    whole run, against the plain D1Q3 path per instance."""
+    import numpy as np
+    import torch
+
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd import vdwlb as V
+    from paper_1805_07251_amd.batch import Batch
+    from paper_1805_07251_amd.lattice import Lattice
+
+    def maxwell(a, b, kT):
+        try:
+            return V.maxwell(a, b, kT)
+        except V.VdwlbError:
+            return None
+
+    ws = I.batch_slabs(maxwell, seed, dim=1)
+    sites = np.array([w.nx for w in ws], dtype=np.float64)
+    C = ws[0].C
+    b = Batch(ws)
+    b.init([w.rho for w in ws])
+    b.run(1000)
+    torch.cuda.synchronize()
+    b.init([w.rho for w in ws])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    st = b.status()
+    done = np.where(st == 0, steps, np.maximum(st - 1, 0))
+    mlups_c = float((sites * done).sum() * C / secs / 1e6)
+    order = np.argsort(sites)
+    subset = [int(order[i]) for i in np.linspace(0, len(ws) - 1, 16).astype(int)]
+    nplain = 2000
+    lats = []
+    for k in subset:
+        lat = Lattice.from_workload(ws[k])
+        lat.init(ws[k].rho)
+        lat.run(64)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.run(nplain)
+    torch.cuda.synchronize()
+    psecs = time.perf_counter() - t0
+    plain_mlups_c = float(sites[subset].sum() * nplain * C / psecs / 1e6)
+    return {
+        "workload": f"{len(ws)} D1Q3 lines, L in [128,1024], C={C}, FP64, slab init, LDS-resident",
+        "steps": steps,
+        "seconds": secs,
+        "mlups_x_c": mlups_c,
+        "instances_stopped_unphysical": int((st != 0).sum()),
+        "plain_per_instance_mlups_x_c": plain_mlups_c,
+        "plain_sample": f"16 instances across the size range, {nplain} steps each, one plan per instance",
+        "speedup_vs_plain_per_instance": mlups_c / plain_mlups_c,
+    }
+
+
 def adjoint_leg(seed):
     """Gradient of a density-profile loss after 2000 steps of the 256 x 256
     lattice w.r.t. (kT, a11, a12, a22, b1, b2, kappa), checkpoints every 100."""
@@ -331,6 +397,8 @@ def main():
         extra["mixture4_1024_f32"] = sweep_line(w2, "f32", 5000, args.warmup)
         extra["copy_kernel_gbs"] = copy_gbs()
         extra["batched"] = batch_leg(args.seed, 20000, 10)
+        extra["d1q3_line_16M_f64"] = sweep_line(I.line_spinodal(args.seed, L=1 << 24), "f64", 2000, args.warmup)
+        extra["batched_d1q3"] = batch_d1q3_leg(args.seed, 50000)
         extra["adjoint"] = adjoint_leg(args.seed)
     out["extra"] = extra
     if not args.no_cpu:
