@@ -21,6 +21,9 @@ Contents
   maxwell_single           liquid-gas coexistence of one component
   coexistence_two_phase    common tangent between two bulk phases (Newton)
   minimize_three_phase     the quasi-brute-force direct search of Appendix A
+  coexistence_three_phase  the three-phase point of a two-component mixture
+                           (equal mu^c and p in all phases; Newton, started
+                           from the direct search)
   gamma_from_width_rule    gamma_mu from Eq. kappaGammaMuRelation
 """
 from __future__ import annotations
@@ -256,6 +259,51 @@ def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_it
     phases = [(A1 / V1, B1 / V1, V1), (A2 / V2, B2 / V2, V2),
               ((NA - A1 - A2) / (1 - V1 - V2), (NB - B1 - B2) / (1 - V1 - V2), 1 - V1 - V2)]
     return phases, F
+
+
+def coexistence_three_phase(phases, kT, a, b, tol=1e-15, maxit=50):
+    """Three coexisting bulk phases of a two-component mixture.
+
+    At fixed temperature the three-phase state of two components has no free
+    variable (Gibbs phase rule): the six densities satisfy six equations,
+    mu^c(phase 1) = mu^c(phase 2) = mu^c(phase 3) for c = A, B and equal
+    pressure (Sec. II).  Newton with the analytic Jacobian (d mu / d rho is
+    the Hessian, d p / d rho = rho^T H by Gibbs-Duhem), started from
+    `phases` (three density pairs, e.g. the direct search of Appendix A).
+    Returns the three density pairs and the final residual norm.
+    """
+    z = np.concatenate([np.asarray(ph, dtype=float) for ph in phases])
+
+    def split(z):
+        return z[0:2], z[2:4], z[4:6]
+
+    def resid(z):
+        r1, r2, r3 = split(z)
+        m1, m2, m3 = (chemical_potential(r, kT, a, b) for r in (r1, r2, r3))
+        p1, p2, p3 = (pressure(r, kT, a, b) for r in (r1, r2, r3))
+        return np.concatenate([m1 - m2, m1 - m3, [p1 - p2, p1 - p3]])
+
+    for _ in range(maxit):
+        F = resid(z)
+        r1, r2, r3 = split(z)
+        H1, H2, H3 = (hessian(r, kT, a, b) for r in (r1, r2, r3))
+        g1, g2, g3 = r1 @ H1, r2 @ H2, r3 @ H3
+        J = np.zeros((6, 6))
+        J[0:2, 0:2], J[0:2, 2:4] = H1, -H2
+        J[2:4, 0:2], J[2:4, 4:6] = H1, -H3
+        J[4, 0:2], J[4, 2:4] = g1, -g2
+        J[5, 0:2], J[5, 4:6] = g1, -g3
+        step = np.linalg.solve(J, F)
+        lam = 1.0
+        while True:
+            t = z - lam * step
+            if all(np.all(r > 0) and np.dot(b, r) < 1 for r in split(t)):
+                break
+            lam *= 0.5
+        z = t
+        if np.max(np.abs(lam * step)) < tol * max(1.0, np.max(np.abs(z))):
+            break
+    return [r.copy() for r in split(z)], float(np.linalg.norm(resid(z)))
 
 
 def gamma_from_width_rule(kappa: float, rho_liquid: float, cs2: float = THETA_LB):

@@ -161,6 +161,35 @@ def test_appendix_a_minimizer_three_phases():
     assert F < T.free_energy_density([0.8, 0.8], kT, a, b)
 
 
+def test_three_phase_point_is_unique():
+    """Gibbs phase rule: two components at fixed temperature have a unique
+    three-phase state.  Newton on equal mu^c and p, started from the Appendix
+    A direct search at two different overall compositions inside the
+    three-phase triangle, reaches the same six densities to round-off, within
+    the direct search's accuracy of its start, and every overall composition
+    used lies inside the triangle of the refined phases (non-negative
+    barycentric weights)."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    kT = 1 / 3
+    refined = []
+    for NA, NB in ((0.8, 0.8), (0.7, 0.9)):
+        phases, _ = T.minimize_three_phase(NA, NB, kT, a, b, threshold=1e-10)
+        start = [np.array([pa, pb]) for pa, pb, V in phases]
+        out, res = T.coexistence_three_phase(start, kT, a, b)
+        assert res < 1e-13
+        for s0, s1 in zip(start, out):
+            assert np.abs(s1 - s0).max() < 1e-3 * np.abs(s0).max()
+        M = np.vstack([np.column_stack(out), np.ones(3)])
+        wts = np.linalg.solve(M, np.array([NA, NB, 1.0]))
+        assert np.all(wts > 0)
+        refined.append(sorted(out, key=lambda r: r[0] - r[1]))
+    for r0, r1 in zip(*refined):
+        np.testing.assert_allclose(r0, r1, rtol=1e-12)
+    mus = np.array([T.chemical_potential(r, kT, a, b) for r in refined[0]])
+    ps = np.array([T.pressure(r, kT, a, b) for r in refined[0]])
+    assert np.ptp(mus, axis=0).max() < 1e-13 and np.ptp(ps) < 1e-14
+
+
 def test_gamma_rule():
     """Eq. kappaGammaMuRelation with c_s^2 = 1/3: 1/3 = 1 - 4 kappa rho_l gamma."""
     g = T.gamma_from_width_rule(0.1, 6.7644704000989)
