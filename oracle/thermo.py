@@ -21,9 +21,9 @@ Contents
   maxwell_single           liquid-gas coexistence of one component
   coexistence_two_phase    common tangent between two bulk phases (Newton)
   minimize_three_phase     the quasi-brute-force direct search of Appendix A
-  coexistence_three_phase  the three-phase point of a two-component mixture
-                           (equal mu^c and p in all phases; Newton, started
-                           from the direct search)
+  coexistence_invariant_point  C + 1 coexisting phases of C components (equal
+                           mu^c and p in all phases; Newton from a start),
+                           coexistence_three_phase the C = 2 case
   gamma_from_width_rule    gamma_mu from Eq. kappaGammaMuRelation
 """
 from __future__ import annotations
@@ -261,38 +261,42 @@ def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_it
     return phases, F
 
 
-def coexistence_three_phase(phases, kT, a, b, tol=1e-15, maxit=50):
-    """Three coexisting bulk phases of a two-component mixture.
+def coexistence_invariant_point(phases, kT, a, b, tol=1e-15, maxit=50):
+    """C + 1 coexisting bulk phases of a C-component mixture.
 
-    At fixed temperature the three-phase state of two components has no free
-    variable (Gibbs phase rule): the six densities satisfy six equations,
-    mu^c(phase 1) = mu^c(phase 2) = mu^c(phase 3) for c = A, B and equal
-    pressure (Sec. II).  Newton with the analytic Jacobian (d mu / d rho is
-    the Hessian, d p / d rho = rho^T H by Gibbs-Duhem), started from
-    `phases` (three density pairs, e.g. the direct search of Appendix A).
-    Returns the three density pairs and the final residual norm.
+    At fixed temperature the state with the maximal number of phases has no
+    free variable (Gibbs phase rule): its (C + 1) C densities satisfy as many
+    equations, mu^c equal in all phases for every c and equal pressure
+    (Sec. II).  Newton with the analytic Jacobian (d mu / d rho is the
+    Hessian, d p / d rho = rho^T H by Gibbs-Duhem), started from `phases`
+    (C + 1 density vectors).  Returns the phases and the residual norm.
     """
+    P = len(phases)
+    C = len(phases[0])
+    assert P == C + 1
     z = np.concatenate([np.asarray(ph, dtype=float) for ph in phases])
-
-    def split(z):
-        return z[0:2], z[2:4], z[4:6]
+    split = lambda z: [z[k * C:(k + 1) * C] for k in range(P)]
 
     def resid(z):
-        r1, r2, r3 = split(z)
-        m1, m2, m3 = (chemical_potential(r, kT, a, b) for r in (r1, r2, r3))
-        p1, p2, p3 = (pressure(r, kT, a, b) for r in (r1, r2, r3))
-        return np.concatenate([m1 - m2, m1 - m3, [p1 - p2, p1 - p3]])
+        rs = split(z)
+        m0, p0 = chemical_potential(rs[0], kT, a, b), pressure(rs[0], kT, a, b)
+        out = [m0 - chemical_potential(r, kT, a, b) for r in rs[1:]]
+        out.append(np.array([p0 - pressure(r, kT, a, b) for r in rs[1:]]))
+        return np.concatenate(out)
 
     for _ in range(maxit):
         F = resid(z)
-        r1, r2, r3 = split(z)
-        H1, H2, H3 = (hessian(r, kT, a, b) for r in (r1, r2, r3))
-        g1, g2, g3 = r1 @ H1, r2 @ H2, r3 @ H3
-        J = np.zeros((6, 6))
-        J[0:2, 0:2], J[0:2, 2:4] = H1, -H2
-        J[2:4, 0:2], J[2:4, 4:6] = H1, -H3
-        J[4, 0:2], J[4, 2:4] = g1, -g2
-        J[5, 0:2], J[5, 4:6] = g1, -g3
+        rs = split(z)
+        Hs = [hessian(r, kT, a, b) for r in rs]
+        gs = [r @ H for r, H in zip(rs, Hs)]
+        n = P * C
+        J = np.zeros((n, n))
+        for k in range(1, P):  # mu rows: (k - 1) C .. k C
+            J[(k - 1) * C:k * C, 0:C] = Hs[0]
+            J[(k - 1) * C:k * C, k * C:(k + 1) * C] = -Hs[k]
+        for k in range(1, P):  # pressure rows
+            J[(P - 1) * C + k - 1, 0:C] = gs[0]
+            J[(P - 1) * C + k - 1, k * C:(k + 1) * C] = -gs[k]
         step = np.linalg.solve(J, F)
         lam = 1.0
         while True:
@@ -304,6 +308,12 @@ def coexistence_three_phase(phases, kT, a, b, tol=1e-15, maxit=50):
         if np.max(np.abs(lam * step)) < tol * max(1.0, np.max(np.abs(z))):
             break
     return [r.copy() for r in split(z)], float(np.linalg.norm(resid(z)))
+
+
+def coexistence_three_phase(phases, kT, a, b, tol=1e-15, maxit=50):
+    """The three-phase point of a two-component mixture (see
+    coexistence_invariant_point), e.g. from the Appendix A direct search."""
+    return coexistence_invariant_point(phases, kT, a, b, tol, maxit)
 
 
 def gamma_from_width_rule(kappa: float, rho_liquid: float, cs2: float = THETA_LB):

@@ -190,6 +190,39 @@ def test_three_phase_point_is_unique():
     assert np.ptp(mus, axis=0).max() < 1e-13 and np.ptp(ps) < 1e-14
 
 
+def test_four_phase_point_of_three_components():
+    """The invariant point of the paper's three-component example (theta_cr =
+    0.5, rho_cr = 1, nu = 0.05, theta = 1/3): Newton reaches the same four
+    phases from two different starts (Gibbs phase rule: no free variable),
+    with equal mu^c and p; each liquid is rich in its own component, the
+    vapour is symmetric, and the density ratio is of the order the paper
+    reports (~1700 there; the exact number depends on kappa-free bulk
+    thermodynamics only through these densities)."""
+    th, rc, nu = 0.5, 1.0, 0.05
+    aa, bb = 9 * th / (8 * rc), 1 / (3 * rc)
+    a = np.full((3, 3), nu * aa)
+    np.fill_diagonal(a, aa)
+    b = np.full(3, bb)
+    kT = 1 / 3
+    rg, rl = T.maxwell_single(aa, bb, kT)
+    s1 = [np.full(3, rg)] + [np.where(np.arange(3) == i, rl, 1e-3) for i in range(3)]
+    s2 = [np.full(3, 0.8 * rg)] + [np.where(np.arange(3) == i, 0.9 * rl, 1e-2) for i in range(3)]
+    p1, r1 = T.coexistence_invariant_point(s1, kT, a, b)
+    p2, r2 = T.coexistence_invariant_point(s2, kT, a, b)
+    assert r1 < 1e-13 and r2 < 1e-13
+    for x, y in zip(p1, p2):
+        np.testing.assert_allclose(x, y, rtol=1e-12)
+    gas, liqs = p1[0], p1[1:]
+    assert np.ptp(gas) < 1e-14 * gas.max()
+    for i, liq in enumerate(liqs):
+        assert liq[i] > 100 * np.delete(liq, i).max()
+    ratio = max(p.max() for p in p1) / min(p.min() for p in p1)
+    assert 500 < ratio < 5000
+    mus = np.array([T.chemical_potential(p, kT, a, b) for p in p1])
+    ps = np.array([T.pressure(p, kT, a, b) for p in p1])
+    assert np.ptp(mus, axis=0).max() < 1e-13 and np.ptp(ps) < 1e-14
+
+
 def test_gamma_rule():
     """Eq. kappaGammaMuRelation with c_s^2 = 1/3: 1/3 = 1 - 4 kappa rho_l gamma."""
     g = T.gamma_from_width_rule(0.1, 6.7644704000989)
