@@ -503,3 +503,40 @@ def test_four_phase_three_component_stress(gpu):
         assert bulk[k].sum() < 0.5
     assert r.max() / r.min() > 1000
     assert dev < 5e-2
+
+
+def test_nid_versus_log_forcing(gpu):
+    """The two forcing discretisations of Sec. V (Eq. forceMuId "nid",
+    Eq. forceMuLog "log") on the same converged single-component slabs
+    (kappa = 0.4, 0.7 and 0.8 kT_crit, 80,000 steps): the log form reaches
+    the Maxwell densities to 1e-6, while the nid form, whose central
+    difference of theta ln rho does not cancel the lattice's ideal pressure
+    exactly, settles measurably away from them (here by more than 10 % in the
+    vapour and 1 % in the liquid).  The paper reports that the two differ in
+    accuracy and stability and uses the log form."""
+    batch, _ = gpu
+    from paper_1805_07251_amd.inputs import A11, B1, KT_CRIT, Workload
+
+    kap = 0.4
+    ws, ref = [], []
+    for force in (0, 1):
+        for t in (0.7, 0.8):
+            rg, rl = T.maxwell_single(A11, B1, t * KT_CRIT)
+            gam = T.gamma_from_width_rule(kap, rl)
+            ws.append(Workload(128, 1, t * KT_CRIT, np.array([[A11]]), np.array([B1]), np.array([[kap]]),
+                               slab_profile(128, 1.1 * rg, 0.97 * rl)[None, None, :], gamma_mu=gam, dim=1,
+                               force=force))
+            ref.append((rg, rl))
+    b = batch_run(batch, ws, [80000])
+    assert np.all(b.status() == 0)
+    dev = []
+    for k, r in enumerate(b.densities()):
+        r = np_(r)[0, 0]
+        rg, rl = ref[k]
+        dev.append((abs(window_mean(r, 0) / rg - 1), abs(window_mean(r, 64) / rl - 1)))
+    print("log (gas, liquid):", [f"{g:.1e}, {l:.1e}" for g, l in dev[:2]],
+          "nid:", [f"{g:.1e}, {l:.1e}" for g, l in dev[2:]])
+    for g, l in dev[:2]:
+        assert g < 1e-6 and l < 1e-6
+    for g, l in dev[2:]:
+        assert g > 0.1 and l > 0.01
