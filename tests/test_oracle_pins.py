@@ -416,3 +416,88 @@ def test_complex_step_matches_finite_difference(orc):
         d_fd = (loss_real(up) - loss_real(dn)) / (2 * hf)
         assert abs(d_cs - d_fd) <= 1e-6 * abs(d_cs) + 1e-12, (idx, d_cs, d_fd)
     assert loss_cx(0, 1e-30).real == pytest.approx(loss_real(base), rel=1e-14)
+
+
+# ---------------------------------------------------------------- pressure tensor
+def _continuum_pxx(r, rp, rpp, kT, a, b, kap):
+    """P_xx of Sec. II for a 1-component field with analytic derivatives:
+    p(rho) - kappa (rho'^2 + rho rho'') + kappa rho'^2 = p(rho) - kappa rho rho''."""
+    p = r * kT / (1 - b * r) - a * r * r
+    return p - kap * r * rpp
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_pressure_tensor_converges_to_continuum(dim):
+    """On a smooth field rho0 + eps sin(k x) the lattice pressure tensor
+    (isotropic gradient and Laplacian stencils) approaches the continuum
+    tensor with analytic derivatives at least at second order in k (halving
+    k cuts the error by 4 or more; in P_xx the kappa (d rho)^2 terms cancel
+    and only the Laplacian's k^4 error is left, a factor 16).  A wrong
+    stencil weight or sign would leave an O(1) error."""
+    from oracle import diagnostics as G
+
+    kT, a, b, kap = 0.45, A11, B1, 0.3
+    errs = []
+    for L in (32, 64, 128):
+        x = np.arange(L)
+        k = 2 * np.pi / L
+        r = 2.6 + 0.4 * np.sin(k * x)
+        rp, rpp = 0.4 * k * np.cos(k * x), -0.4 * k * k * np.sin(k * x)
+        field = np.tile(r, (4, 1)) if dim == 2 else r[None, :]
+        pxx, pyy, pxy = G.pressure_tensor(field[None], kT, [[a]], [b], [[kap]], dim=dim)
+        want = _continuum_pxx(r, rp, rpp, kT, a, b, kap)
+        errs.append(np.abs(pxx[0] - want).max())
+        if dim == 2:
+            # y-uniform field: P_yy has no kappa d_y d_y term, P_xy = 0
+            want_yy = r * kT / (1 - b * r) - a * r * r - kap * (rp ** 2 + r * rpp)
+            assert np.abs(pyy[0] - want_yy).max() < 50 * k * k
+            assert np.abs(pxy).max() < 1e-14
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+    assert errs[2] < 1e-6
+
+
+def test_pressure_tensor_symmetries():
+    """Transposing a D2Q9 field swaps P_xx and P_yy and keeps P_xy; mirroring
+    x flips the sign of P_xy; a uniform field has P = p(rho) delta (Sec. II
+    bulk pressure)."""
+    from oracle import diagnostics as G
+
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(1.0, 3.0, (2, 12, 12))
+    a = np.array([[A11, 0.8 * A11], [0.8 * A11, A11]])
+    b = np.array([B1, 1.1 * B1])
+    kap = np.array([[0.1, 0.07], [0.07, 0.12]])
+    kT = 0.4
+    pxx, pyy, pxy = G.pressure_tensor(rho, kT, a, b, kap)
+    txx, tyy, txy = G.pressure_tensor(rho.transpose(0, 2, 1), kT, a, b, kap)
+    np.testing.assert_allclose(txx, pyy.T, rtol=1e-13)
+    np.testing.assert_allclose(tyy, pxx.T, rtol=1e-13)
+    np.testing.assert_allclose(txy, pxy.T, rtol=1e-12, atol=1e-14)
+    mxx, myy, mxy = G.pressure_tensor(rho[:, :, ::-1], kT, a, b, kap)
+    np.testing.assert_allclose(mxy, -pxy[:, ::-1], rtol=1e-12, atol=1e-14)
+    u = np.ones((2, 5, 7)) * np.array([1.2, 2.1])[:, None, None]
+    uxx, uyy, uxy = G.pressure_tensor(u, kT, a, b, kap)
+    p = T.pressure([1.2, 2.1], kT, a, b)
+    assert np.abs(uxx - p).max() < 1e-13 and np.abs(uyy - p).max() < 1e-13 and np.abs(uxy).max() == 0
+
+
+def test_pressure_tensor_bulk_of_converged_interface(orc):
+    """Converged D1Q3 slab (kappa = 0.4): in the bulk phases P_xx equals the
+    bulk pressure of the Maxwell construction to round-off; through the
+    interface it varies (the paper attributes the interface discrepancies to
+    higher-order gradient terms)."""
+    from oracle import diagnostics as G
+
+    kT = 0.8 * KTC
+    rg, rl = T.maxwell_single(A11, B1, kT)
+    gam = T.gamma_from_width_rule(0.4, rl)
+    p = orc.Params(kT, np.array([[A11]]), np.array([B1]), np.array([[0.4]]), gamma_mu=gam)
+    L = 128
+    lat = orc.Lattice(p, 1, L, 1)
+    lat.init(slab(L, rg, rl)[None, None, :])
+    assert lat.run(40000) == 0
+    rho = lat.moments()[0]
+    pxx, _, _ = G.pressure_tensor(rho, kT, p.a, p.b, p.kappa, dim=1)
+    pm = T.pressure([rl], kT, p.a, p.b)
+    assert abs(pxx[0, L // 2] - pm) < 1e-9 * abs(pm)
+    assert abs(pxx[0, 0] - pm) < 1e-9 * abs(pm)
