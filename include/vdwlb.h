@@ -156,6 +156,20 @@ vdwlb_status vdwlb_step(vdwlb_plan* plan, void* fA, void* fB, int64_t n, void* s
  * what vdwlb_sync_status would. */
 vdwlb_status vdwlb_moments(vdwlb_plan* plan, const void* f, void* rho, void* mom, void* mu, void* p, void* stream);
 
+/* Pressure tensor of Sec. II (the tensor that satisfies Eq. GibbsDuehem for
+ * the mixture free energy) of a density field, with the lattice's isotropic
+ * stencils for the derivatives:
+ *   P_ab = sum_c [rho^c kT/(1-eta) - sum_c' a^{cc'} rho^c rho^c'
+ *                 - sum_c' kappa^{cc'} (grad rho^c . grad rho^c' + rho^c Lap rho^c')] delta_ab
+ *          + sum_cc' kappa^{cc'} d_a rho^c d_b rho^c'
+ * A diagnostic: in bulk phases it is the bulk pressure; across interfaces
+ * it carries the higher-order gradient terms the paper discusses.
+ *   rho  device, [C][ny][nx] in the plan dtype (e.g. from vdwlb_moments), read.
+ *   pxx  device, [ny][nx], written.  pyy, pxy: same, or NULL to skip (for a
+ *        D1Q3 plan P_yy is the isotropic part and P_xy = 0).
+ * Asynchronous on stream. */
+vdwlb_status vdwlb_pressure_tensor(vdwlb_plan* plan, const void* rho, void* pxx, void* pyy, void* pxy, void* stream);
+
 /* Synchronise stream, read and clear the sticky device flag of the plan. */
 vdwlb_status vdwlb_sync_status(vdwlb_plan* plan, void* stream);
 

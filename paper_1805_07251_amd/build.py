@@ -34,7 +34,7 @@ FLAGS = [
     "-packed-fp32-ops",
 ]
 
-SOURCES = ["api.cpp", "runtime.hip", "sweep_f64.hip", "sweep_f32.hip", "batch.hip", "adjoint.hip"]
+SOURCES = ["api.cpp", "runtime.hip", "sweep_f64.hip", "sweep_f32.hip", "batch.hip", "adjoint.hip", "diag.hip"]
 
 
 def _hipcc() -> str:

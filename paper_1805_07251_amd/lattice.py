@@ -138,6 +138,19 @@ class Lattice:
         t = self._field(f, (self.C, self.Q, self.ny, self.nx)).reshape(self.C, self.Q, n)
         self.state[:, :n, :].copy_(t.permute(1, 2, 0))
 
+    def pressure_tensor(self, rho=None, stream=None):
+        """(P_xx, P_yy, P_xy), each [ny, nx], of the density field rho
+        [C, ny, nx] (default: the current state's densities)."""
+        if rho is None:
+            rho = self.moments(want_mu=False, want_p=False, stream=stream)[0]
+        r = self._field(rho, (self.C, self.ny, self.nx))
+        kw = dict(dtype=self.plan.torch_dtype, device=self.device)
+        out = [torch.empty((self.ny, self.nx), **kw) for _ in range(3)]
+        V.check(V.lib().vdwlb_pressure_tensor(self.plan.handle, r.data_ptr(), *[t.data_ptr() for t in out],
+                                              _stream_ptr(stream)), "vdwlb_pressure_tensor")
+        self._keep_p = r  # the input stays alive until the stream has consumed it
+        return tuple(out)
+
     def moments(self, want_mu=True, want_p=True, stream=None):
         """rho [C,ny,nx], mom [C,2,ny,nx], mu [C,ny,nx] or None, p [ny,nx] or None.
         Raises VdwlbError(E_UNPHYSICAL) if the sticky device flag is set."""
