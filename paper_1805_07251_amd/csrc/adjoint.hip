@@ -302,21 +302,21 @@ __global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F
     if (threadIdx.x < NP) partial[(int64_t)blockIdx.x * NP + threadIdx.x] = s_red[threadIdx.x][0];
 }
 
-// Fixed-order reduction of the per-workgroup partials into pbar (+=).
-__global__ void k_adj_reduce(const double* __restrict__ partial, int nblocks, int np, double* __restrict__ pbar) {
+// Fixed-order reduction of the per-workgroup partials of a whole segment
+// (n vectors of np entries) into pbar (+=): workgroup q sums entry q.
+__global__ void __launch_bounds__(BLK) k_adj_reduce(const double* __restrict__ partial, int n, int np,
+                                                     double* __restrict__ pbar) {
     __shared__ double s[BLK];
-    for (int q = 0; q < np; ++q) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += BLK) a += partial[(int64_t)b * np + q];
-        s[threadIdx.x] = a;
-        __syncthreads();
-        for (int h = BLK / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) pbar[q] += s[0];
+    const int q = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < n; b += BLK) a += partial[(int64_t)b * np + q];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = BLK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0) pbar[q] += s[0];
 }
 
 // Kernel C: total density cotangent and the un-streamed population cotangent.
@@ -369,6 +369,11 @@ __global__ void __launch_bounds__(BLK) k_moments_adj(const double* __restrict__ 
 
 using namespace vdwlb;
 
+void vdwlb::release_adjoint_graph(vdwlb_plan& p) {
+    if (p.adj.exec) (void)hipGraphExecDestroy(p.adj.exec);
+    p.adj = AdjointGraph{};
+}
+
 namespace {
 
 struct Layout {
@@ -395,8 +400,8 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
     o += (int64_t)nsteps * 3 * p.C * L.N;
     L.fields = o;
     o += 13 * (int64_t)p.C * L.N;
-    L.partial = o;
-    o += (int64_t)L.nb_b * L.np;
+    L.partial = o;  // one partial vector per workgroup of kernel B and per step
+    o += (int64_t)nsteps * L.nb_b * L.np;
     L.total = o;
     return L;
 }
@@ -420,17 +425,45 @@ adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
 
 template <int C>
 hipError_t adjoint_step(const vdwlb_plan& p, const Layout& L, double* ws, int t, const double* fbn, double* fbo,
-                        double* pbar, hipStream_t s) {
+                        hipStream_t s) {
     Geometry g = make_geometry(p, adj::TX, adj::TY);
     const Coeffs<C> k = make_coeffs<C>(p);
     adj::Fields F = fields_at(p, L, ws, t);
     const int tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
     hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k, F);
-    hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, F, ws + L.partial);
-    hipLaunchKernelGGL(adj::k_adj_reduce, dim3(1), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial), L.nb_b,
-                       L.np, pbar);
+    hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, F,
+                       ws + L.partial + (int64_t)t * L.nb_b * L.np);
     hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega, F);
     return hipGetLastError();
+}
+
+// Forward recompute of a segment from the checkpoint already in the
+// workspace (keeping each step's moments), then the reverse sweep from
+// fbar_io; the result ends in fbar_io.
+hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* fbar_io,
+                           double* pbar, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < nsteps && e == hipSuccess; ++t) {
+        double* cur = ws + ((t & 1) ? L.f1 : L.f0);
+        double* nxt = ws + ((t & 1) ? L.f0 : L.f1);
+        double* m = ws + L.moms + (int64_t)t * 3 * p.C * L.N;
+        e = launch_moments(p, cur, m, m + (int64_t)p.C * L.N, nullptr, nullptr, s);
+        if (e == hipSuccess) e = launch_sweep(p, cur, nxt, s);
+    }
+    double* bufs[2] = {fbar_io, ws + L.fb};
+    for (int t = nsteps - 1, k = 0; t >= 0 && e == hipSuccess; --t, ++k) {
+        const double* fbn = bufs[k & 1];
+        double* fbo = bufs[(k + 1) & 1];
+        e = p.C == 1 ? adjoint_step<1>(p, L, ws, t, fbn, fbo, s) : adjoint_step<2>(p, L, ws, t, fbn, fbo, s);
+    }
+    if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
+        hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
+                           nsteps * L.nb_b, L.np, pbar);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && (nsteps & 1))
+        e = hipMemcpyAsync(fbar_io, ws + L.fb, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return e;
 }
 
 }  // namespace
@@ -470,33 +503,45 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
     if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const Layout L = layout(*p, nsteps);
+    if ((int64_t)nsteps * L.nb_b > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
     double* ws = (double*)workspace;
-    const size_t sb = (size_t)L.state * sizeof(double);
-    // forward recompute from the checkpoint, keeping the moments of each step
-    hipError_t e = hipMemcpyAsync(ws + L.f0, f_ckpt, sb, hipMemcpyDeviceToDevice, s);
+    // the checkpoint goes into the workspace eagerly, so a captured segment
+    // does not depend on where the caller keeps its checkpoints
+    hipError_t e = hipMemcpyAsync(ws + L.f0, f_ckpt, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return set_device_error(e, "adjoint checkpoint copy");
-    for (int t = 0; t < nsteps; ++t) {
-        double* cur = ws + ((t & 1) ? L.f1 : L.f0);
-        double* nxt = ws + ((t & 1) ? L.f0 : L.f1);
-        double* m = ws + L.moms + (int64_t)t * 3 * p->C * L.N;
-        e = launch_moments(*p, cur, m, m + (int64_t)p->C * L.N, nullptr, nullptr, s);
-        if (e == hipSuccess) e = launch_sweep(*p, cur, nxt, s);
-        if (e != hipSuccess) return set_device_error(e, "adjoint forward recompute");
+    if (!graphs_enabled()) {
+        e = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, s);
+        return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint segment");
     }
-    // reverse sweep: fbar_io <-> workspace buffer
-    double* bufs[2] = {(double*)fbar_io, ws + L.fb};
-    for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
-        const double* fbn = bufs[k & 1];
-        double* fbo = bufs[(k + 1) & 1];
-        e = p->C == 1 ? adjoint_step<1>(*p, L, ws, t, fbn, fbo, pbar_accum, s)
-                      : adjoint_step<2>(*p, L, ws, t, fbn, fbo, pbar_accum, s);
-        if (e != hipSuccess) return set_device_error(e, "adjoint step");
+    AdjointGraph& G = p->adj;
+    if (!(G.exec && G.nsteps == nsteps && G.fbar == fbar_io && G.ws == workspace && G.pbar == pbar_accum &&
+          G.sched == p->sched && G.map_mode == p->map_mode)) {
+        release_adjoint_graph(*p);
+        if (!p->capture_stream) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return set_device_error(e, "adjoint capture");
+        const hipError_t le = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, p->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->capture_stream, &g);
+        if (le != hipSuccess || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return set_device_error(le != hipSuccess ? le : e, "adjoint capture");
+        }
+        e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            G.exec = nullptr;
+            return set_device_error(e, "adjoint graph instantiate");
+        }
+        G.nsteps = nsteps;
+        G.fbar = fbar_io;
+        G.ws = workspace;
+        G.pbar = pbar_accum;
+        G.sched = p->sched;
+        G.map_mode = p->map_mode;
     }
-    if (nsteps & 1) {
-        e = hipMemcpyAsync(fbar_io, ws + L.fb, sb, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return set_device_error(e, "adjoint result copy");
-    }
-    return VDWLB_OK;
+    e = hipGraphLaunch(G.exec, s);
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint graph launch");
 }
 
 }  // extern "C"

@@ -139,6 +139,7 @@ vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out) {
 vdwlb_status vdwlb_plan_destroy(vdwlb_plan* p) {
     if (!p) return VDWLB_OK;
     release_graph(*p);
+    release_adjoint_graph(*p);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     if (p->d_flag) (void)hipFree(p->d_flag);
     delete p;

@@ -8,6 +8,13 @@
 
 #include "../../include/vdwlb.h"
 
+// Captured adjoint segment, bound to its step count, buffers and schedule.
+struct AdjointGraph {
+    hipGraphExec_t exec = nullptr;
+    int nsteps = 0, sched = -1, map_mode = -1;
+    const void *fbar = nullptr, *ws = nullptr, *pbar = nullptr;
+};
+
 struct vdwlb_plan {
     int dim = 2, nx = 0, ny = 0, C = 0, dtype = 0, force = 0;
     double kT = 0, tau = 1, gamma = 1;
@@ -22,6 +29,7 @@ struct vdwlb_plan {
     const void* gA = nullptr;
     const void* gB = nullptr;
     hipStream_t capture_stream = nullptr;
+    AdjointGraph adj;
 };
 
 namespace vdwlb {
@@ -54,6 +62,7 @@ inline bool state_aligned(const vdwlb_plan& p, const void* f) {
 bool apply_public_schedule(vdwlb_plan& p, int k);
 int default_schedule(const vdwlb_plan& p);
 bool graphs_enabled();
+void release_adjoint_graph(vdwlb_plan& p);
 
 hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
 hipError_t launch_init(const vdwlb_plan& p, void* f, const void* rho, const void* mom, hipStream_t s);
