@@ -447,8 +447,7 @@ hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int
         double* cur = ws + ((t & 1) ? L.f1 : L.f0);
         double* nxt = ws + ((t & 1) ? L.f0 : L.f1);
         double* m = ws + L.moms + (int64_t)t * 3 * p.C * L.N;
-        e = launch_moments(p, cur, m, m + (int64_t)p.C * L.N, nullptr, nullptr, s);
-        if (e == hipSuccess) e = launch_sweep(p, cur, nxt, s);
+        e = launch_sweep(p, cur, nxt, s, m);  // the sweep also writes this step's moments
     }
     double* bufs[2] = {fbar_io, ws + L.fb};
     for (int t = nsteps - 1, k = 0; t >= 0 && e == hipSuccess; --t, ++k) {

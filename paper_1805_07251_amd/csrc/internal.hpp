@@ -64,7 +64,9 @@ int default_schedule(const vdwlb_plan& p);
 bool graphs_enabled();
 void release_adjoint_graph(vdwlb_plan& p);
 
-hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
+// mom: null, or [C][N] densities then [C][2][N] momenta of the pulled state
+// (D2Q9 plans only).
+hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom = nullptr);
 hipError_t launch_init(const vdwlb_plan& p, void* f, const void* rho, const void* mom, hipStream_t s);
 hipError_t launch_moments(const vdwlb_plan& p, const void* f, void* rho, void* mom, void* mu, void* pr,
                           hipStream_t s);

@@ -1,6 +1,8 @@
 // Host-side launch helpers shared by the per-precision dispatch units.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "schedules.hpp"
 #include "sweep.hpp"
@@ -43,24 +45,36 @@ Coeffs<C> make_coeffs(const vdwlb_plan& p) {
 }
 
 template <typename T, int C, int TX, int TY, bool NTS, int OCC>
-hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     const Geometry g = make_geometry(p, TX, TY);
     const Coeffs<C> k = make_coeffs<C>(p);
     const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
+    if (mom) {  // the adjoint's recompute: FP64, C <= 2 only
+        if constexpr (std::is_same<T, double>::value && C <= 2) {
+            if (p.tau == 1.0)
+                hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, true, true>), dim3(tiles), dim3(TX * TY), 0, s,
+                                   (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+            else
+                hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, false, true>), dim3(tiles), dim3(TX * TY), 0, s,
+                                   (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (p.tau == 1.0)
         hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, true>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
-                           (T*)fout, g, k, p.d_flag);
+                           (T*)fout, g, k, p.d_flag, (T*)nullptr);
     else
         hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, false>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
-                           (T*)fout, g, k, p.d_flag);
+                           (T*)fout, g, k, p.d_flag, (T*)nullptr);
     return hipGetLastError();
 }
 
 template <typename T, int C>
-hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     switch (p.sched) {
 #define VDWLB_SCHED_CASE(i, tx, ty, nt, occ) \
-    case i: return run_sweep<T, C, tx, ty, nt, occ>(p, fin, fout, s);
+    case i: return run_sweep<T, C, tx, ty, nt, occ>(p, fin, fout, s, mom);
         VDWLB_SCHEDULES(VDWLB_SCHED_CASE)
 #undef VDWLB_SCHED_CASE
         default: return hipErrorInvalidValue;
@@ -90,8 +104,9 @@ hipError_t run_sweep1(const vdwlb_plan& p, const void* fin, void* fout, hipStrea
 }
 
 template <typename T, int C>
-hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     if (p.dim == 1) {
+        if (mom) return hipErrorInvalidValue;  // the moments output is a D2Q9 feature
         switch (p.sched) {
 #define VDWLB_SCHED1_CASE(i, tx, nt) \
     case i: return run_sweep1<T, C, tx, nt>(p, fin, fout, s);
@@ -100,21 +115,21 @@ hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t
             default: return hipErrorInvalidValue;
         }
     }
-    return run_sweep_sched<T, C>(p, fin, fout, s);
+    return run_sweep_sched<T, C>(p, fin, fout, s, mom);
 }
 
 template <typename T>
-hipError_t run_sweep_typed(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
+hipError_t run_sweep_typed(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     switch (p.C) {
-        case 1: return run_any<T, 1>(p, fin, fout, s);
-        case 2: return run_any<T, 2>(p, fin, fout, s);
-        case 3: return run_any<T, 3>(p, fin, fout, s);
-        case 4: return run_any<T, 4>(p, fin, fout, s);
+        case 1: return run_any<T, 1>(p, fin, fout, s, mom);
+        case 2: return run_any<T, 2>(p, fin, fout, s, mom);
+        case 3: return run_any<T, 3>(p, fin, fout, s, mom);
+        case 4: return run_any<T, 4>(p, fin, fout, s, mom);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep_f64(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
-hipError_t launch_sweep_f32(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s);
+hipError_t launch_sweep_f64(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom);
+hipError_t launch_sweep_f32(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom);
 
 }  // namespace vdwlb

@@ -35,8 +35,8 @@ bool graphs_enabled() {
     return !(v && v[0] == '1');
 }
 
-hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
-    return p.dtype == VDWLB_F64 ? launch_sweep_f64(p, fin, fout, s) : launch_sweep_f32(p, fin, fout, s);
+hipError_t launch_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
+    return p.dtype == VDWLB_F64 ? launch_sweep_f64(p, fin, fout, s, mom) : launch_sweep_f32(p, fin, fout, s, mom);
 }
 
 namespace {

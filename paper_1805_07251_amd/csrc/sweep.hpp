@@ -480,6 +480,8 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
 }
 
 // The plain sweep: one launch per time step, one workgroup per TX x TY tile.
+// MOM: also write the moments rho^c and j^c of the pulled state to mom_out,
+// as the adjoint's forward recompute keeps them.
 // Phase 1 pulls the 9C populations of each interior site into registers
 // (reused by the collision unless tau = 1) and the densities of the radius-2 ring around the
 // tile (re-read from L2/MALL, never stored) into LDS; phase 2 evaluates the
@@ -488,9 +490,10 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
 // NTSTORE: non-temporal stores of the new state, so that output lines do not
 // displace halo lines in L2.  OCC > 0 asks the compiler for at least OCC waves
 // per SIMD (a VGPR budget of 512 / OCC).
-template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC, bool TAU1>
+template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC, bool TAU1, bool MOM = false>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
-k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k, int* __restrict__ flag) {
+k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k, int* __restrict__ flag,
+        T* __restrict__ mom_out) {
     constexpr int NT = TX * TY, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
     constexpr int RING = EX * EY - TX * TY;
     __shared__ T s_rho[C][EY * EX];
@@ -517,6 +520,15 @@ k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k
             pin(jy[c]);
         }
         s_rho[c][(ly + 2) * EX + lx + 2] = rho[c];
+    }
+    if (MOM && x < g.nx && y < g.ny) {  // moments of the pulled state: rho [C][N], then j [C][2][N]
+        const int64_t n = (int64_t)g.nx * g.ny, site = (int64_t)y * g.nx + x;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mom_out[c * n + site] = rho[c];
+            mom_out[(C + 2 * c) * n + site] = jx[c];
+            mom_out[(C + 2 * c + 1) * n + site] = jy[c];
+        }
     }
     for (int r = threadIdx.x; r < RING; r += NT) {
         int ex, ey;

@@ -2,7 +2,7 @@
 #include "launch.hpp"
 
 namespace vdwlb {
-hipError_t launch_sweep_f64(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
-    return run_sweep_typed<double>(p, fin, fout, s);
+hipError_t launch_sweep_f64(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
+    return run_sweep_typed<double>(p, fin, fout, s, mom);
 }
 }  // namespace vdwlb
