@@ -282,10 +282,15 @@ def test_flat_interface_equilibrium_single_component(orc):
     assert lat.run(40000) == 0
     rho, mom, mu, pr, _ = lat.moments()
     assert np.ptp(mu) < 1e-9
+    # the central difference leaves an odd-even mode: check each sublattice
+    assert np.ptp(mu[..., 0::2]) < 1e-9 and np.ptp(mu[..., 1::2]) < 1e-9
     liq, gas = rho[0, 0, L // 2], rho[0, 0, 0]
     assert abs(liq - rl) < 1e-7 * rl
     assert abs(gas - rg) < 1e-7 * rg
-    assert abs(pr[0, L // 2] - pr[0, 0]) < 1e-7
+    # bulk pressures: 7e-8 relative here, and no smaller at 80,000 steps; the
+    # pressure still varies by as much within 8 sites of the slab centre, so
+    # on a 128-site line the bound is set by interface tails, not convergence
+    assert abs(pr[0, L // 2] - pr[0, 0]) < 2e-7 * abs(pr[0, 0])
     # static state: the physical momentum j + G/2 vanishes, so j = -G/2 is
     # the only momentum left (Appendix of the force derivation)
     assert np.abs(mom).max() > 1e-3
