@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn
         gy[c] = g0y[c];
     }
     if constexpr (C == 2) {
-        const double lam = k.lam[0][1];
+        const double lam = k.lam(0, 1);
         m = rho[0] * rho[1] / (rho[0] + rho[1]);
         K = lam / (1.0 + 0.5 * lam);
         d0x = (jx[1] + 0.5 * g0x[1]) / rho[1] - (jx[0] + 0.5 * g0x[0]) / rho[0];
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int d = 0; d < C; ++d) {
-                double J = k.kT * ((k.b[c] + k.b[d]) * iv + k.b[c] * k.b[d] * tot * iv * iv) - k.a2[c][d];
+                double J = k.kT * ((k.b[c] + k.b[d]) * iv + k.b[c] * k.b[d] * tot * iv * iv) - k.a2(c, d);
                 if (c == d) J += k.kT / rho[c];
                 rb[d] += mub[c] * J;
             }
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F
         for (int d = 0; d < C; ++d) {
             double lt = F.lb[(int64_t)d * N + s];
 #pragma unroll
-            for (int c = 0; c < C; ++c) lt -= mub[c] * k.kap[c][d];
+            for (int c = 0; c < C; ++c) lt -= mub[c] * k.kap(c, d);
             F.lb_tot[(int64_t)d * N + s] = lt;
             F.rhob_b[(int64_t)d * N + s] = rb[d];
         }

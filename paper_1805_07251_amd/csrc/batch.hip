@@ -42,9 +42,9 @@ __device__ __forceinline__ void put_wrapped(T* plane, int row, int e, T v) {
 // only the x ring is recomputed.  Executed by TX * NY threads.  Every site
 // goes through the same arithmetic as in the plain sweep (same functions and
 // stencil expressions), so results are bit-identical to it.
-template <typename T, int C, int TX, int NY, bool NTSTORE, bool TAU1>
+template <typename T, int C, int TX, int NY, bool NTSTORE, bool TAU1, typename R>
 __device__ __forceinline__ bool strip_step(const T* __restrict__ fin, T* __restrict__ fout, const Geometry& g,
-                                           const Coeffs<C>& k, int x0, T* s_rho, T* s_phi) {
+                                           const Coeffs<C, R>& k, int x0, T* s_rho, T* s_phi) {
     using L = StripLds<TX, NY>;
     constexpr int NT = TX * NY, EX = L::EX, MX = L::MX;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
@@ -121,9 +121,9 @@ struct Instance {
 
 // Friction and D1Q3 collision of one site, the new populations written to
 // the LDS state [i][c][x] (same arithmetic as collide_store1).
-template <typename T, int C, bool TAU1>
+template <typename T, int C, bool TAU1, typename R>
 __device__ __forceinline__ void collide_lds1(T (&p)[C][Q1], const T (&rho)[C], T (&jx)[C], T (&gx)[C],
-                                             const T (&lap)[C], const Coeffs<C>& k, T* sf, int lmax, int x) {
+                                             const T (&lap)[C], const Coeffs<C, R>& k, T* sf, int lmax, int x) {
     T ri[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) ri[c] = recip(rho[c]);
@@ -136,7 +136,7 @@ __device__ __forceinline__ void collide_lds1(T (&p)[C][Q1], const T (&rho)[C], T
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) * recip(ri[c] + ri[d]);
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam(c, d)) * recip(ri[c] + ri[d]);
         friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
     }
 #pragma unroll

@@ -14,7 +14,7 @@ namespace {
 
 template <typename T, int C, int DIM>
 __global__ void __launch_bounds__(256) k_ptensor(const T* __restrict__ rho, T* __restrict__ pxx, T* __restrict__ pyy,
-                                                 T* __restrict__ pxy, int nx, int ny, Coeffs<C> k) {
+                                                 T* __restrict__ pxy, int nx, int ny, Coeffs<C, T> k) {
     const int n = nx * ny;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -51,8 +51,8 @@ __global__ void __launch_bounds__(256) k_ptensor(const T* __restrict__ rho, T* _
     for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int d = 0; d < C; ++d) {
-            const T kap = T(k.kap[c][d]);
-            scalar -= T(0.5) * T(k.a2[c][d]) * r[c] * r[d] + kap * ((gx[c] * gx[d] + gy[c] * gy[d]) + r[c] * lap[d]);
+            const T kap = T(k.kap(c, d));
+            scalar -= T(0.5) * T(k.a2(c, d)) * r[c] * r[d] + kap * ((gx[c] * gx[d] + gy[c] * gy[d]) + r[c] * lap[d]);
             txx += kap * gx[c] * gx[d];
             tyy += kap * gy[c] * gy[d];
             txy += kap * gx[c] * gy[d];
@@ -66,7 +66,7 @@ template <typename T, int C>
 hipError_t ptensor_c(const vdwlb_plan& p, const void* rho, void* pxx, void* pyy, void* pxy, hipStream_t s) {
     const int n = p.nx * p.ny;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    const Coeffs<C> k = make_coeffs<C>(p);
+    const Coeffs<C, T> k = make_coeffs<C, T>(p);
     if (p.dim == 1)
         hipLaunchKernelGGL((k_ptensor<T, C, 1>), dim3(nb), dim3(256), 0, s, (const T*)rho, (T*)pxx, (T*)pyy, (T*)pxy,
                            p.nx, p.ny, k);

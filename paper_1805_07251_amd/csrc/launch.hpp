@@ -23,23 +23,27 @@ inline Geometry make_geometry(const vdwlb_plan& p, int tx, int ty) {
     return g;
 }
 
-template <int C>
-Coeffs<C> make_coeffs(const vdwlb_plan& p) {
-    Coeffs<C> k;
-    k.kT = p.kT;
-    k.omega = 1.0 / p.tau;
-    k.cG = (p.tau - 0.25) / p.tau;
-    k.cL = 1.0 / (12.0 * p.tau);
-    k.gamma = p.gamma;
+// Kernel coefficients in the kernel's own precision R (each value computed in
+// double and rounded once); the symmetric matrices keep one triangle.
+template <int C, typename R = double>
+Coeffs<C, R> make_coeffs(const vdwlb_plan& p) {
+    using K = Coeffs<C, R>;
+    K k;
+    k.kT = R(p.kT);
+    k.omega = R(1.0 / p.tau);
+    k.cG = R((p.tau - 0.25) / p.tau);
+    k.cL = R(1.0 / (12.0 * p.tau));
+    k.gamma = R(p.gamma);
+    k.lamt[0] = R(0);
     for (int c = 0; c < C; ++c) {
-        k.b[c] = p.b[c];
-        for (int d = 0; d < C; ++d) {
-            k.a2[c][d] = 2.0 * p.a[c * C + d];
-            k.kap[c][d] = p.kappa[c * C + d];
-            k.lam[c][d] = p.lam[c * C + d];
+        k.b[c] = R(p.b[c]);
+        for (int d = c; d < C; ++d) {
+            k.a2t[K::tri(c, d)] = R(2.0 * p.a[c * C + d]);
+            k.kapt[K::tri(c, d)] = R(p.kappa[c * C + d]);
+            if (d > c) k.lamt[K::off(c, d)] = R(p.lam[c * C + d]);
         }
     }
-    k.fk = C >= 2 ? 1.0 / (1.0 + 0.5 * p.lam[1]) : 0.0;
+    k.fk = R(C >= 2 ? 1.0 / (1.0 + 0.5 * p.lam[1]) : 0.0);
     k.force = p.force;
     return k;
 }
@@ -47,7 +51,7 @@ Coeffs<C> make_coeffs(const vdwlb_plan& p) {
 template <typename T, int C, int TX, int TY, bool NTS, int OCC>
 hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     const Geometry g = make_geometry(p, TX, TY);
-    const Coeffs<C> k = make_coeffs<C>(p);
+    const Coeffs<C, T> k = make_coeffs<C, T>(p);
     const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
     if (mom) {  // the adjoint's recompute: FP64, C <= 2 only
         if constexpr (std::is_same<T, double>::value && C <= 2) {
@@ -92,7 +96,7 @@ inline Geometry1 make_geometry1(const vdwlb_plan& p, int tx) {
 template <typename T, int C, int TX, bool NTS>
 hipError_t run_sweep1(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s) {
     const Geometry1 g = make_geometry1(p, TX);
-    const Coeffs<C> k = make_coeffs<C>(p);
+    const Coeffs<C, T> k = make_coeffs<C, T>(p);
     const int tiles = (p.nx + TX - 1) / TX;
     if (p.tau == 1.0)
         hipLaunchKernelGGL((k_sweep1<T, C, TX, NTS, true>), dim3(tiles), dim3(TX), 0, s, (const T*)fin, (T*)fout, g,

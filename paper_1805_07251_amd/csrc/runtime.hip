@@ -65,7 +65,7 @@ hipError_t moments_c(const vdwlb_plan& p, const void* f, void* rho, void* mom, v
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || (!mu && !pr)) return e;
         hipLaunchKernelGGL((k_mu_p1<T, C>), dim3(nb), dim3(256), 0, s, (const T*)rho, (T*)mu, (T*)pr, g1,
-                           make_coeffs<C>(p), p.d_flag);
+                           make_coeffs<C, T>(p), p.d_flag);
         return hipGetLastError();
     }
     const Geometry g = make_geometry(p, 64, 1);
@@ -75,7 +75,7 @@ hipError_t moments_c(const vdwlb_plan& p, const void* f, void* rho, void* mom, v
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!mu && !pr)) return e;
     hipLaunchKernelGGL((k_mu_p<T, C>), dim3((n + 255) / 256), dim3(256), 0, s, (const T*)rho, (T*)mu, (T*)pr, g,
-                       make_coeffs<C>(p), p.d_flag);
+                       make_coeffs<C, T>(p), p.d_flag);
     return hipGetLastError();
 }
 

@@ -38,19 +38,30 @@ struct Geometry {
 };
 
 // Coefficients of one lattice, precomputed on the host in double.
-template <int C>
+template <int C, typename R = double>
 struct Coeffs {
-    double kT;
-    double omega;  // 1/tau
-    double cG;     // (tau - 1/4)/tau: coefficient of G G / rho in S
-    double cL;     // 1/(12 tau): coefficient of Lap(rho) in S
-    double gamma;  // gamma_mu
-    double a2[C][C];
-    double kap[C][C];
-    double lam[C][C];
-    double b[C];
-    double fk;  // 1 / (1 + lambda^{01}/2): closed-form friction factor for C = 2
+    static constexpr int NTRI = C * (C + 1) / 2;           // upper triangle with the diagonal
+    static constexpr int NOFF = C > 1 ? C * (C - 1) / 2 : 1;  // strictly upper triangle
+    R kT;
+    R omega;  // 1/tau
+    R cG;     // (tau - 1/4)/tau: coefficient of G G / rho in S
+    R cL;     // 1/(12 tau): coefficient of Lap(rho) in S
+    R gamma;  // gamma_mu
+    R a2t[NTRI];   // 2 a^{cc'} (symmetric: one triangle kept, so C = 4 fits the scalar registers)
+    R kapt[NTRI];  // kappa^{cc'}
+    R lamt[NOFF];  // lambda^{cc'}, c != c'
+    R b[C];
+    R fk;  // 1 / (1 + lambda^{01}/2): closed-form friction factor for C = 2
     int force;  // 0 log, 1 nid
+    __host__ __device__ static constexpr int tri(int c, int d) {
+        return c <= d ? c * C - c * (c - 1) / 2 + (d - c) : d * C - d * (d - 1) / 2 + (c - d);
+    }
+    __host__ __device__ static constexpr int off(int c, int d) {
+        return c < d ? c * (2 * C - c - 1) / 2 + (d - c - 1) : d * (2 * C - d - 1) / 2 + (c - d - 1);
+    }
+    __host__ __device__ R a2(int c, int d) const { return a2t[tri(c, d)]; }
+    __host__ __device__ R kap(int c, int d) const { return kapt[tri(c, d)]; }
+    __host__ __device__ R lam(int c, int d) const { return c == d ? R(0) : lamt[off(c, d)]; }
 };
 
 constexpr double THETA = 1.0 / 3.0;
@@ -275,8 +286,8 @@ __device__ __forceinline__ bool finite_val(T v) {
 // with 2 sum psi rho(x + dx) = -2 a rho - kappa Lap(rho)) and the potential
 // phi whose gradient drives the force: gamma mu (log) or
 // gamma mu - theta ln rho (nid).  Returns false for unphysical input.
-template <typename T, int C>
-__device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], const Coeffs<C>& k, T (&phi)[C]) {
+template <typename T, int C, typename R>
+__device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], const Coeffs<C, R>& k, T (&phi)[C]) {
     T eta = T(0), tot = T(0);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -291,7 +302,7 @@ __device__ __forceinline__ bool potential(const T (&rho)[C], const T (&lap)[C], 
         ok = ok && rho[c] > T(0);
         T mu = T(k.kT) * (dlog(rho[c] * inv) + T(k.b[c]) * tot * inv);
 #pragma unroll
-        for (int d = 0; d < C; ++d) mu -= T(k.a2[c][d]) * rho[d] + T(k.kap[c][d]) * lap[d];
+        for (int d = 0; d < C; ++d) mu -= T(k.a2(c, d)) * rho[d] + T(k.kap(c, d)) * lap[d];
         phi[c] = T(k.gamma) * mu;
         if (k.force == 1) phi[c] -= T(THETA) * dlog(rho[c]);
         ok = ok && finite_val(phi[c]);
@@ -327,12 +338,13 @@ __device__ __forceinline__ void friction(const T (&rho)[C], const T (&ri)[C], co
             A[c][c] = diag;
             r[c] = j[c] + T(0.5) * g[c];
         }
+        T ip[C];  // reciprocals of the pivots, reused by the back substitution
 #pragma unroll
         for (int p = 0; p < C; ++p) {
-            const T ip = T(1) / A[p][p];
+            ip[p] = recip(A[p][p]);
 #pragma unroll
             for (int q = p + 1; q < C; ++q) {
-                const T f = A[q][p] * ip;
+                const T f = A[q][p] * ip[p];
 #pragma unroll
                 for (int m = p; m < C; ++m) A[q][m] -= f * A[p][m];
                 r[q] -= f * r[p];
@@ -343,7 +355,7 @@ __device__ __forceinline__ void friction(const T (&rho)[C], const T (&ri)[C], co
             T acc = r[p];
 #pragma unroll
             for (int m = p + 1; m < C; ++m) acc -= A[p][m] * uh[m];
-            uh[p] = acc / A[p][p];
+            uh[p] = acc * ip[p];
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -446,9 +458,9 @@ __device__ __forceinline__ void pull_density(const T* __restrict__ f, const Geom
 
 // Friction, collision and store of one site whose pulled populations p,
 // density, momentum, mean-field force g and density Laplacian are known.
-template <typename T, int C, bool NTSTORE, bool TAU1>
+template <typename T, int C, bool NTSTORE, bool TAU1, typename R>
 __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T (&jx)[C], T (&jy)[C], T (&gx)[C],
-                                              T (&gy)[C], const T (&lap)[C], const Coeffs<C>& k,
+                                              T (&gy)[C], const T (&lap)[C], const Coeffs<C, R>& k,
                                               T* __restrict__ fout, int64_t plane, int s) {
     T ri[C];
 #pragma unroll
@@ -463,7 +475,7 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) * recip(ri[c] + ri[d]);
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam(c, d)) * recip(ri[c] + ri[d]);
         friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
         friction<T, C>(rho, ri, jy, gy, W, T(k.fk));
     }
@@ -492,7 +504,7 @@ __device__ __forceinline__ void collide_store(T (&p)[C][Q], const T (&rho)[C], T
 // per SIMD (a VGPR budget of 512 / OCC).
 template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC, bool TAU1, bool MOM = false>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
-k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C> k, int* __restrict__ flag,
+k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C, T> k, int* __restrict__ flag,
         T* __restrict__ mom_out) {
     constexpr int NT = TX * TY, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
     constexpr int RING = EX * EY - TX * TY;
@@ -629,7 +641,7 @@ __global__ void k_moments(const T* __restrict__ f, T* __restrict__ rho, T* __res
 // mu^c (Eq. discreteChemicalPotential without the constant kT) and the bulk
 // pressure of Sec. II from a density field.
 template <typename T, int C>
-__global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restrict__ pr, Geometry g, Coeffs<C> k,
+__global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restrict__ pr, Geometry g, Coeffs<C, T> k,
                        int* __restrict__ flag) {
     const int n = g.nx * g.ny;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -646,7 +658,7 @@ __global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restr
         const T diag = (R[yp * g.nx + xp] + R[yp * g.nx + xm]) + (R[ym * g.nx + xm] + R[ym * g.nx + xp]);
         l[c] = (T(4) * axis + diag - T(20) * r[c]) * T(1.0 / 6.0);
     }
-    Coeffs<C> kk = k;
+    Coeffs<C, T> kk = k;
     kk.gamma = 1.0;
     kk.force = 0;
     T m[C];
@@ -662,7 +674,7 @@ __global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restr
             eta += T(k.b[c]) * r[c];
             tot += r[c];
 #pragma unroll
-            for (int d = 0; d < C; ++d) att += T(0.5) * T(k.a2[c][d]) * r[c] * r[d];
+            for (int d = 0; d < C; ++d) att += T(0.5) * T(k.a2(c, d)) * r[c] * r[d];
         }
         pr[s] = tot * T(k.kT) / (T(1) - eta) - att;
     }

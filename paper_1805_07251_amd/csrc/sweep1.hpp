@@ -80,9 +80,9 @@ __device__ __forceinline__ void collide1(T (&p)[Q1], T rho, T ri, T jx, T gx, T 
 
 // Friction, collision and store of one site (x components only: in 1-D the
 // momenta and forces have no y part).
-template <typename T, int C, bool NTSTORE, bool TAU1>
+template <typename T, int C, bool NTSTORE, bool TAU1, typename R>
 __device__ __forceinline__ void collide_store1(T (&p)[C][Q1], const T (&rho)[C], T (&jx)[C], T (&gx)[C],
-                                               const T (&lap)[C], const Coeffs<C>& k, T* __restrict__ fout,
+                                               const T (&lap)[C], const Coeffs<C, R>& k, T* __restrict__ fout,
                                                int64_t plane, int x) {
     T ri[C];
 #pragma unroll
@@ -96,7 +96,7 @@ __device__ __forceinline__ void collide_store1(T (&p)[C][Q1], const T (&rho)[C],
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam[c][d]) * recip(ri[c] + ri[d]);
+            for (int d = c + 1; d < C; ++d) W[c][d] = W[d][c] = T(k.lam(c, d)) * recip(ri[c] + ri[d]);
         friction<T, C>(rho, ri, jx, gx, W, T(k.fk));
     }
 #pragma unroll
@@ -117,7 +117,7 @@ __device__ __forceinline__ void collide_store1(T (&p)[C][Q1], const T (&rho)[C],
 // applies friction and collision and stores.
 template <typename T, int C, int TX, bool NTSTORE, bool TAU1>
 __global__ void __launch_bounds__(TX) k_sweep1(const T* __restrict__ fin, T* __restrict__ fout, Geometry1 g,
-                                                Coeffs<C> k, int* __restrict__ flag) {
+                                                Coeffs<C, T> k, int* __restrict__ flag) {
     constexpr int EX = TX + 4, MX = TX + 2;
     __shared__ T s_rho[C][EX];
     __shared__ T s_phi[C][MX];
@@ -217,7 +217,7 @@ __global__ void k_moments1(const T* __restrict__ f, T* __restrict__ rho, T* __re
 // mu^c (Eq. discreteChemicalPotential without the constant kT) and the bulk
 // pressure of Sec. II from a 1-D density field.
 template <typename T, int C>
-__global__ void k_mu_p1(const T* __restrict__ rho, T* __restrict__ mu, T* __restrict__ pr, Geometry1 g, Coeffs<C> k,
+__global__ void k_mu_p1(const T* __restrict__ rho, T* __restrict__ mu, T* __restrict__ pr, Geometry1 g, Coeffs<C, T> k,
                         int* __restrict__ flag) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= g.nx) return;
@@ -229,7 +229,7 @@ __global__ void k_mu_p1(const T* __restrict__ rho, T* __restrict__ mu, T* __rest
         r[c] = R[x];
         l[c] = lap3<T>(R[xm], r[c], R[xp]);
     }
-    Coeffs<C> kk = k;
+    Coeffs<C, T> kk = k;
     kk.gamma = 1.0;
     kk.force = 0;
     T m[C];
@@ -244,7 +244,7 @@ __global__ void k_mu_p1(const T* __restrict__ rho, T* __restrict__ mu, T* __rest
             eta += T(k.b[c]) * r[c];
             tot += r[c];
 #pragma unroll
-            for (int d = 0; d < C; ++d) att += T(0.5) * T(k.a2[c][d]) * r[c] * r[d];
+            for (int d = 0; d < C; ++d) att += T(0.5) * T(k.a2(c, d)) * r[c] * r[d];
         }
         pr[x] = tot * T(k.kT) / (T(1) - eta) - att;
     }
