@@ -10,9 +10,11 @@ value      MLUPS x components (million site updates per second times C), inputs
 roofline   the sweep kernel against the 8 TB/s HBM peak, with algorithmic bytes
            2 * 9 * C * sizeof(real) per site update.
 cpu_baseline  the CPU oracle on the host, a bounded sample of the same workload.
-extra      FP32 and 4-component sweeps, the batched phase-diagram workload in
-           D2Q9 (strips through L2/MALL) and D1Q3 (instances resident in LDS),
-           a 2^24-site D1Q3 line, and the adjoint against the plain forward.
+extra      the headline's median over 5 separate runs, with init, readback and
+           host copies timed on their own; FP32 and 4-component sweeps; the
+           batched phase-diagram workload in D2Q9 (strips through L2/MALL) and
+           D1Q3 (instances resident in LDS); a 2^24-site D1Q3 line; and the
+           adjoint against the plain forward.
 """
 from __future__ import annotations
 
@@ -88,6 +90,62 @@ def sweep_line(w, dtype, steps, warmup, schedule=-1):
         "bytes_per_site": bytes_per_site,
         "schedule": sched,
         "status": st,
+    }
+
+
+def protocol_leg(w, dtype, schedule, repeats=5, steps=1000):
+    """Timings kept out of the headline: the spread of `repeats` separate runs of
+    `steps` steps (median reported), the init kernel from a density field already
+    in HBM, the moments readback (rho, j, mu, p; the call ends with the error-flag
+    poll, so it is a wall-clock figure), and the host <-> device copies of rho."""
+    import statistics
+
+    import torch
+
+    from paper_1805_07251_amd.lattice import Lattice
+
+    lat = Lattice.from_workload(w, dtype=dtype)
+    lat.set_schedule(schedule)
+    tdt = lat.plan.torch_dtype
+    host = torch.as_tensor(w.rho, dtype=tdt).pin_memory()
+    dev = torch.empty(host.shape, dtype=tdt, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = time.perf_counter() - t0
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat.init(dev)
+    torch.cuda.synchronize()
+    e0.record(s)
+    lat.init(dev)
+    e1.record(s)
+    torch.cuda.synchronize()
+    init_us = e0.elapsed_time(e1) * 1e3
+    runs = [time_steps(lat, steps, 2) / steps * 1e6 for _ in range(repeats)]
+    lat.moments()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho, _, _, _ = lat.moments()
+    moments_us = (time.perf_counter() - t0) * 1e6
+    back = torch.empty(rho.shape, dtype=tdt).pin_memory()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    back.copy_(rho, non_blocking=True)
+    torch.cuda.synchronize()
+    d2h = time.perf_counter() - t0
+    nbytes = host.numel() * host.element_size()
+    return {
+        "repeats_us_per_step": runs,
+        "median_us_per_step": statistics.median(runs),
+        "steps_per_repeat": steps,
+        "init_us": init_us,
+        "moments_readback_us": moments_us,
+        "rho_h2d_ms": h2d * 1e3,
+        "rho_d2h_ms": d2h * 1e3,
+        "rho_bytes": nbytes,
+        "status": lat.status(),
     }
 
 
@@ -391,6 +449,7 @@ def main():
     }
     extra = {}
     if not args.no_extra:
+        extra["headline_protocol"] = protocol_leg(w, "f64", head["schedule"])
         extra["spinodal_2048_f32"] = sweep_line(I.spinodal_large(args.seed, dtype="f32"), "f32", args.steps,
                                                 args.warmup)
         w2 = I.mixture4(args.seed)
