@@ -21,6 +21,9 @@ Contents
   maxwell_single           liquid-gas coexistence of one component
   coexistence_two_phase    common tangent between two bulk phases (Newton)
   minimize_three_phase     the quasi-brute-force direct search of Appendix A
+                           (direct_search also returns its iteration count)
+  phase_point              one (A, B) point of a phase diagram: stability test,
+                           direct search, classification, Newton polish
   coexistence_invariant_point  C + 1 coexisting phases of C components (equal
                            mu^c and p in all phases; Newton from a start),
                            coexistence_three_phase the C = 2 case
@@ -212,10 +215,34 @@ def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_it
     split follows the unstable eigenvector of the Hessian at (NA, NB).
     Returns a list of (rho_A, rho_B, V) per phase with V > 0.
     """
-    rho0 = np.array([NA, NB], dtype=float)
-    H = hessian(rho0, kT, a, b)
-    w, v = np.linalg.eigh(H)
-    d = v[:, 0]
+    phases, F, _ = direct_search(NA, NB, kT, a, b, threshold, max_iter)
+    return phases, F
+
+
+def unstable_direction(H):
+    """Unit eigenvector of the lowest eigenvalue of the symmetric 2 x 2 H,
+    with its sign fixed (first component >= 0; the second > 0 if the first
+    is zero): the paper only says the split follows this eigenvector."""
+    w, v = np.linalg.eigh(np.asarray(H, dtype=float))
+    d = v[:, 0].copy()
+    if d[0] < 0 or (d[0] == 0 and d[1] < 0):
+        d = -d
+    return d
+
+
+def direct_search(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000):
+    """The search of minimize_three_phase; also returns the iteration count.
+
+    Start: phases 1 and 2 take half of each species, displaced by
+    +-eps/2 d along the unstable direction d (eps = 0.05 min(NA, NB)), with
+    volume 0.499 each; phase 3 starts with 1e-4 of each species and volume
+    0.002 (a phase with zero particles but a volume has no finite free energy
+    in the form used here, and one-coordinate moves could never fill it).
+    Initial step 0.01.  Trial order: variable k = A1, B1, V1, A2, B2, V2, the
+    + move before the - move; the first strict minimum wins.
+    """
+    NA, NB = float(NA), float(NB)
+    d = unstable_direction(hessian(np.array([NA, NB]), kT, a, b))
     eps = 0.05 * min(NA, NB)
 
     def total(z):
@@ -233,7 +260,6 @@ def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_it
             F += V * free_energy_density(r, kT, a, b)
         return F
 
-    # phase 1 and 2 split along the unstable direction, phase 3 small
     z = np.array([0.5 * NA + 0.5 * eps * d[0], 0.5 * NB + 0.5 * eps * d[1], 0.499,
                   0.5 * NA - 0.5 * eps * d[0] - 1e-4 * NA, 0.5 * NB - 0.5 * eps * d[1] - 1e-4 * NB, 0.499])
     F = total(z)
@@ -258,7 +284,112 @@ def minimize_three_phase(NA: float, NB: float, kT, a, b, threshold=1e-12, max_it
     A1, B1, V1, A2, B2, V2 = z
     phases = [(A1 / V1, B1 / V1, V1), (A2 / V2, B2 / V2, V2),
               ((NA - A1 - A2) / (1 - V1 - V2), (NB - B1 - B2) / (1 - V1 - V2), 1 - V1 - V2)]
-    return phases, F
+    return phases, F, it
+
+
+# Classification constants of the phase-diagram pipeline (step 6 of Appendix A)
+MERGE_TOL = 1e-3   # phases whose densities differ by less (max norm, relative to max(1, |rho|)) are one phase
+VOLUME_MIN = 1e-6  # merged phases with a smaller volume are dropped
+POLISH_MAX = 5e-2  # a Newton polish that moves a density further than this is rejected
+
+
+def _stable(r, kT, a, b):
+    H = hessian(r, kT, a, b)
+    return H[0, 0] > 0 and H[0, 0] * H[1, 1] - H[0, 1] * H[1, 0] > 0
+
+
+def phase_point(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000):
+    """One (A, B) point of the phase diagram of a two-component mixture
+    (Appendix A): stability test, direct search, classification, and a Newton
+    polish of the coexistence conditions.
+
+    status: -1 invalid overall composition (a density <= 0 or eta >= 1);
+             1 stable (Hessian positive definite): no search (step 2a);
+             otherwise the number of distinct phases the search ends with (2 or
+             3), or 0 if it ends with an infinite free energy.
+    Distinct phases: the search's three phases merged greedily in their
+    order when their densities agree within MERGE_TOL, the merged density
+    being total particles over total volume; then phases with volume below
+    VOLUME_MIN dropped; sorted by rho_A - rho_B ascending.
+    Polish: with 2 phases Newton on equal mu^c, equal p and the lever rule
+    through (NA, NB) (coexistence_two_phase); with 3 phases Newton on equal
+    mu^c and p in all three (coexistence_three_phase), the volumes then from
+    the lever rule.  Accepted when finite, the volumes lie in (0, 1) and no
+    density moves by more than POLISH_MAX; otherwise, with three phases, the
+    closest two are merged and the pair polished as two phases (status 2);
+    if that is rejected too the raw distinct phases are kept.
+    Returns a dict with phases [(rho_A, rho_B, V)], raw (the search's three
+    phases), F, iterations, n_unstable (distinct phases whose Hessian is not
+    positive definite) and polished (0 not attempted, 1 accepted, 2 rejected).
+    """
+    NA, NB = float(NA), float(NB)
+    N = np.array([NA, NB])
+    out = dict(phases=[], raw=[], F=np.nan, iterations=0, n_unstable=0, polished=0, status=-1)
+    if not (NA > 0 and NB > 0 and np.dot(b, N) < 1):
+        return out
+    out["F"] = free_energy_density(N, kT, a, b)
+    if _stable(N, kT, a, b):
+        out.update(phases=[(NA, NB, 1.0)], status=1)
+        return out
+    raw, F, it = direct_search(NA, NB, kT, a, b, threshold, max_iter)
+    out.update(raw=raw, F=F, iterations=it)
+    if not np.isfinite(F):
+        out["status"] = 0
+        return out
+    groups = []  # [particles A, particles B, volume]
+    for ra, rb, V in raw:
+        r = np.array([ra, rb])
+        for g in groups:
+            rg = np.array([g[0] / g[2], g[1] / g[2]])
+            if np.max(np.abs(r - rg)) <= MERGE_TOL * max(1.0, np.max(np.abs(rg))):
+                g[0] += ra * V
+                g[1] += rb * V
+                g[2] += V
+                break
+        else:
+            groups.append([ra * V, rb * V, V])
+    ph = [(g[0] / g[2], g[1] / g[2], g[2]) for g in groups if g[2] >= VOLUME_MIN]
+    ph.sort(key=lambda p: p[0] - p[1])
+    out["n_unstable"] = sum(not _stable(np.array(p[:2]), kT, a, b) for p in ph)
+    out["phases"] = ph
+    out["status"] = len(ph)
+    if len(ph) not in (2, 3):
+        return out
+    new = _polish(N, ph, kT, a, b)
+    if new is None and len(ph) == 3:
+        # a search stopped at its iteration cap can leave two nearly equal
+        # phases: merge the closest pair and polish as two phases
+        pairs = [(0, 1), (0, 2), (1, 2)]
+        i, j = min(pairs, key=lambda q: max(abs(ph[q[0]][0] - ph[q[1]][0]), abs(ph[q[0]][1] - ph[q[1]][1])))
+        k = 3 - i - j
+        V = ph[i][2] + ph[j][2]
+        m = ((ph[i][0] * ph[i][2] + ph[j][0] * ph[j][2]) / V, (ph[i][1] * ph[i][2] + ph[j][1] * ph[j][2]) / V, V)
+        two = sorted([m, ph[k]], key=lambda p: p[0] - p[1])
+        new = _polish(N, two, kT, a, b)
+        if new is not None:
+            out["status"] = 2
+            out["n_unstable"] = sum(not _stable(np.array(p[:2]), kT, a, b) for p in two)
+    if new is not None:
+        out["phases"] = new
+        out["polished"] = 1
+    else:
+        out["polished"] = 2
+    return out
+
+
+def _polish(N, ph, kT, a, b):
+    """Newton polish of 2 or 3 phases (see phase_point); None if rejected."""
+    if len(ph) == 2:
+        xa, xb, phi = coexistence_two_phase(N, ph[0][:2], ph[1][:2], kT, a, b)
+        new = [(xa[0], xa[1], phi), (xb[0], xb[1], 1.0 - phi)]
+    else:
+        rs, _ = coexistence_three_phase([np.array(p[:2]) for p in ph], kT, a, b)
+        M = np.vstack([np.column_stack(rs), np.ones(3)])
+        vol = np.linalg.solve(M, np.array([N[0], N[1], 1.0]))
+        new = [(r[0], r[1], v) for r, v in zip(rs, vol)]
+    ok = all(np.isfinite(x) for p in new for x in p) and all(0 < p[2] < 1 for p in new)
+    ok = ok and max(max(abs(p[0] - q[0]), abs(p[1] - q[1])) for p, q in zip(new, ph)) <= POLISH_MAX
+    return new if ok else None
 
 
 def coexistence_invariant_point(phases, kT, a, b, tol=1e-15, maxit=50):

@@ -227,3 +227,54 @@ def test_gamma_rule():
     """Eq. kappaGammaMuRelation with c_s^2 = 1/3: 1/3 = 1 - 4 kappa rho_l gamma."""
     g = T.gamma_from_width_rule(0.1, 6.7644704000989)
     assert 1 - 4 * 0.1 * 6.7644704000989 * g == pytest.approx(1 / 3, rel=1e-15)
+
+
+def test_phase_point_identical_components():
+    """Two identical components with neutral interaction (Fig.
+    graphTwoIdenticalComponents, nu = 1): the mixing entropy is linear in the
+    total density at fixed composition, so a point inside the two-phase
+    region splits into a gas and a liquid of its own composition whose total
+    densities are the pure fluid's Maxwell values (tie lines through the
+    origin).  The Appendix A pipeline must find exactly that; a point above
+    the liquid density is stable (no search), and one at or beyond the
+    excluded-volume line is rejected."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 1.0)
+    kT = 1 / 3
+    gas, liq = T.maxwell_single(a[0, 0], b[0], kT)
+    r = T.phase_point(0.3, 0.9, kT, a, b)
+    assert r["status"] == 2 and r["polished"] == 1 and r["n_unstable"] == 0
+    assert r["iterations"] < 5000
+    (ga, gb, vg), (la, lb, vl) = sorted(r["phases"], key=lambda p: p[0] + p[1])
+    np.testing.assert_allclose([ga + gb, la + lb], [gas, liq], rtol=1e-12)
+    np.testing.assert_allclose([ga / (ga + gb), la / (la + lb)], [0.25, 0.25], rtol=1e-12)
+    np.testing.assert_allclose(vg * gas + vl * liq, 1.2, rtol=1e-12)
+    np.testing.assert_allclose(vg + vl, 1.0, rtol=1e-14)
+    # the raw search (before the polish) is already within the paper's ~1e-6
+    raw = sorted(r["raw"], key=lambda p: p[0] + p[1])
+    assert abs(raw[0][0] + raw[0][1] - gas) < 1e-5 and abs(raw[-1][0] + raw[-1][1] - liq) < 1e-5
+    s = T.phase_point(1.0, 1.0, kT, a, b)
+    assert s["status"] == 1 and s["iterations"] == 0 and s["phases"] == [(1.0, 1.0, 1.0)]
+    assert T.phase_point(1.5, 1.5, kT, a, b)["status"] == -1
+    assert T.phase_point(0.0, 0.5, kT, a, b)["status"] == -1
+
+
+def test_phase_point_three_phase_region():
+    """Inside the baseline three-phase triangle (Fig. graphBaselineNa008Nb008)
+    the pipeline reports three phases whose polished densities are the
+    mixture's unique three-phase point (equal mu^c and p, Gibbs phase rule),
+    with lever-rule volumes that reproduce the overall composition."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    kT = 1 / 3
+    r = T.phase_point(0.8, 0.8, kT, a, b)
+    assert r["status"] == 3 and r["polished"] == 1 and r["n_unstable"] == 0
+    rs = [np.array(p[:2]) for p in r["phases"]]
+    mus = np.array([T.chemical_potential(x, kT, a, b) for x in rs])
+    ps = np.array([T.pressure(x, kT, a, b) for x in rs])
+    assert np.ptp(mus, axis=0).max() < 1e-13 and np.ptp(ps) < 1e-14
+    vol = np.array([p[2] for p in r["phases"]])
+    np.testing.assert_allclose(sum(v * x for v, x in zip(vol, rs)), [0.8, 0.8], rtol=1e-12)
+    np.testing.assert_allclose(vol.sum(), 1.0, rtol=1e-14)
+    # B-rich liquid first (sorted by rho_A - rho_B), then the vapour, then A-rich
+    assert rs[0][1] > rs[0][0] and rs[2][0] > rs[2][1] and rs[1].sum() < rs[0].sum()
+    d = T.unstable_direction(T.hessian(np.array([0.8, 0.8]), kT, a, b))
+    assert d[0] >= 0 and abs(np.linalg.norm(d) - 1) < 1e-15
