@@ -230,38 +230,64 @@ def unstable_direction(H):
     return d
 
 
+def _free_energy_ext(rho, kT, a, b):
+    """free_energy_density extended to empty components (rho^c ln rho^c -> 0)."""
+    rho = np.asarray(rho, dtype=float)
+    g = 1.0 - _eta(rho, b)
+    ent = sum(rho[c] * kT * np.log(rho[c] / g) for c in range(rho.size) if rho[c] > 0)
+    return float(ent - rho @ a @ rho)
+
+
 def direct_search(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000):
     """The search of minimize_three_phase; also returns the iteration count.
 
-    Start: phases 1 and 2 take half of each species, displaced by
-    +-eps/2 d along the unstable direction d (eps = 0.05 min(NA, NB)), with
-    volume 0.499 each; phase 3 starts with 1e-4 of each species and volume
-    0.002 (a phase with zero particles but a volume has no finite free energy
-    in the form used here, and one-coordinate moves could never fill it).
-    Initial step 0.01.  Trial order: variable k = A1, B1, V1, A2, B2, V2, the
-    + move before the - move; the first strict minimum wins.
+    Start (step 3 of Appendix A): phase 3 empty; phases 1 and 2 share the
+    particles, displaced by +-eps/2 d along the unstable direction d
+    (eps = 0.05 min(NA, NB)), phase 2 holding exactly what phase 1 does not.
+    The volumes are 1/3 each as printed while the overall packing
+    eta_N = b . N is at most 1/3; above that the empty phase gets
+    (1 - eta_N)/2 and phases 1 and 2 the rest in equal parts, which keeps
+    them below the excluded-volume limit (the printed thirds would pack them
+    to 1.5 eta_N) and is continuous at eta_N = 1/3.  An empty component
+    contributes nothing to the free energy (rho ln rho -> 0), so phase 3 can
+    start empty with a volume; negative amounts are inadmissible.  Initial
+    step 0.01.  Trial order: variable k = A1, B1, V1, A2, B2, V2, the + move
+    before the - move; the first strict minimum wins.  A phase of zero volume
+    is reported with zero densities.
     """
     NA, NB = float(NA), float(NB)
     d = unstable_direction(hessian(np.array([NA, NB]), kT, a, b))
     eps = 0.05 * min(NA, NB)
+    V3 = min(1.0 / 3.0, 0.5 * (1.0 - (b[0] * NA + b[1] * NB)))
+    V12 = 0.5 * (1.0 - V3)
+    A1 = 0.5 * NA + 0.5 * eps * d[0]
+    B1 = 0.5 * NB + 0.5 * eps * d[1]
+    return search_from(NA, NB, [A1, B1, V12, NA - A1, NB - B1, V12], kT, a, b, threshold, max_iter)
+
+
+def search_from(NA, NB, z, kT, a, b, threshold=1e-12, max_iter=200000):
+    """The direct search of Appendix A from the amounts z = (A1, B1, V1, A2,
+    B2, V2), phase 3 holding the rest of (NA, NB) and of the unit volume."""
+    NA, NB = float(NA), float(NB)
+    z = np.array(z, dtype=float)
 
     def total(z):
         A1, B1, V1, A2, B2, V2 = z
         A3, B3, V3 = NA - A1 - A2, NB - B1 - B2, 1.0 - V1 - V2
         F = 0.0
         for A, B, V in ((A1, B1, V1), (A2, B2, V2), (A3, B3, V3)):
-            if V <= 0 or A <= 0 or B <= 0:
-                if V == 0 and A == 0 and B == 0:
+            if V < 0 or A < 0 or B < 0:
+                return np.inf
+            if V == 0:
+                if A == 0 and B == 0:
                     continue
                 return np.inf
             r = np.array([A / V, B / V])
             if np.dot(b, r) >= 1:
                 return np.inf
-            F += V * free_energy_density(r, kT, a, b)
+            F += V * _free_energy_ext(r, kT, a, b)
         return F
 
-    z = np.array([0.5 * NA + 0.5 * eps * d[0], 0.5 * NB + 0.5 * eps * d[1], 0.499,
-                  0.5 * NA - 0.5 * eps * d[0] - 1e-4 * NA, 0.5 * NB - 0.5 * eps * d[1] - 1e-4 * NB, 0.499])
     F = total(z)
     step = 0.01
     it = 0
@@ -282,15 +308,17 @@ def direct_search(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=2000
             if step < threshold:
                 break
     A1, B1, V1, A2, B2, V2 = z
-    phases = [(A1 / V1, B1 / V1, V1), (A2 / V2, B2 / V2, V2),
-              ((NA - A1 - A2) / (1 - V1 - V2), (NB - B1 - B2) / (1 - V1 - V2), 1 - V1 - V2)]
+    phases = []
+    for A, B, V in ((A1, B1, V1), (A2, B2, V2), (NA - A1 - A2, NB - B1 - B2, 1.0 - V1 - V2)):
+        phases.append((A / V, B / V, V) if V > 0 else (0.0, 0.0, V))
     return phases, F, it
 
 
 # Classification constants of the phase-diagram pipeline (step 6 of Appendix A)
 MERGE_TOL = 1e-3   # phases whose densities differ by less (max norm, relative to max(1, |rho|)) are one phase
 VOLUME_MIN = 1e-6  # merged phases with a smaller volume are dropped
-POLISH_MAX = 5e-2  # a Newton polish that moves a density further than this is rejected
+F_SLACK = 1e-12    # a polish may not raise the free energy by more than this (relative to max(1, |F|))
+RESTARTS = 2       # restarts of step 6(b) when a phase is left unstable
 
 
 def _stable(r, kT, a, b):
@@ -303,6 +331,12 @@ def phase_point(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000
     (Appendix A): stability test, direct search, classification, and a Newton
     polish of the coexistence conditions.
 
+    Step 6(b): while a distinct phase is unstable (at most RESTARTS times),
+    the search starts again with the largest unstable phase split along its
+    unstable direction into phases 1 and 2 (eps = 0.05 of its smaller
+    amount) and phase 3 holding the other phases packed together; the
+    iterations of all searches add up.
+
     status: -1 invalid overall composition (a density <= 0 or eta >= 1);
              1 stable (Hessian positive definite): no search (step 2a);
              otherwise the number of distinct phases the search ends with (2 or
@@ -314,10 +348,16 @@ def phase_point(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000
     Polish: with 2 phases Newton on equal mu^c, equal p and the lever rule
     through (NA, NB) (coexistence_two_phase); with 3 phases Newton on equal
     mu^c and p in all three (coexistence_three_phase), the volumes then from
-    the lever rule.  Accepted when finite, the volumes lie in (0, 1) and no
-    density moves by more than POLISH_MAX; otherwise, with three phases, the
-    closest two are merged and the pair polished as two phases (status 2);
-    if that is rejected too the raw distinct phases are kept.
+    the lever rule.  Accepted when finite, every volume lies in (0, 1), the
+    phases stay distinct (the trivial root of these equations has equal
+    phases), each is locally stable (positive-definite Hessian), and their
+    free energy sum_k V_k f(rho_k) does not exceed the search's by more than
+    F_SLACK.  A rejected three-phase polish merges the closest two phases and
+    polishes the pair (status 2), and if that is rejected too drops the
+    phase of smallest volume and polishes the other two; if every polish is
+    rejected the search's distinct phases are kept.  The search supplies the phase count and the
+    start; the polish makes the result exact even where the search stopped
+    at its iteration cap before converging.
     Returns a dict with phases [(rho_A, rho_B, V)], raw (the search's three
     phases), F, iterations, n_unstable (distinct phases whose Hessian is not
     positive definite) and polished (0 not attempted, 1 accepted, 2 rejected).
@@ -332,12 +372,72 @@ def phase_point(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000
         out.update(phases=[(NA, NB, 1.0)], status=1)
         return out
     raw, F, it = direct_search(NA, NB, kT, a, b, threshold, max_iter)
-    out.update(raw=raw, F=F, iterations=it)
-    if not np.isfinite(F):
-        out["status"] = 0
+    restarts = 0
+    while True:
+        out.update(raw=raw, F=F, iterations=out["iterations"] + it)
+        if not np.isfinite(F):
+            out["status"] = 0
+            return out
+        ph = _distinct_phases(raw)
+        unstable = [p for p in ph if not _stable(np.array(p[:2]), kT, a, b)]
+        if unstable and restarts < RESTARTS:
+            # step 6(b): split the (largest) unstable phase along its unstable
+            # direction into phases 1 and 2; phase 3 holds the others packed
+            u = unstable[0]
+            for p in unstable[1:]:
+                if p[2] > u[2]:
+                    u = p
+            Au, Bu, Vu = u[0] * u[2], u[1] * u[2], u[2]
+            d = unstable_direction(hessian(np.array(u[:2]), kT, a, b))
+            eps = 0.05 * min(Au, Bu)
+            A1 = 0.5 * Au + 0.5 * eps * d[0]
+            B1 = 0.5 * Bu + 0.5 * eps * d[1]
+            raw, F, it = search_from(NA, NB, [A1, B1, 0.5 * Vu, Au - A1, Bu - B1, 0.5 * Vu], kT, a, b, threshold,
+                                     max_iter)
+            restarts += 1
+            continue
+        break
+    out["n_unstable"] = len(unstable)
+    out["phases"] = ph
+    out["status"] = len(ph)
+    if len(ph) not in (2, 3):
         return out
+    new = _polish(N, ph, F, kT, a, b)
+    if new is None and len(ph) == 3:
+        # a search stopped at its iteration cap can leave two nearly equal
+        # phases: merge the closest pair and polish as two phases
+        pairs = [(0, 1), (0, 2), (1, 2)]
+        i, j = min(pairs, key=lambda q: max(abs(ph[q[0]][0] - ph[q[1]][0]), abs(ph[q[0]][1] - ph[q[1]][1])))
+        k = 3 - i - j
+        V = ph[i][2] + ph[j][2]
+        m = ((ph[i][0] * ph[i][2] + ph[j][0] * ph[j][2]) / V, (ph[i][1] * ph[i][2] + ph[j][1] * ph[j][2]) / V, V)
+        two = sorted([m, ph[k]], key=lambda p: p[0] - p[1])
+        new = _polish(N, two, F, kT, a, b)
+        if new is None:
+            # or the smallest phase is a seed the search left behind: drop it
+            k = min(range(3), key=lambda q: ph[q][2])
+            two = [ph[q] for q in range(3) if q != k]
+            new = _polish(N, two, F, kT, a, b)
+        if new is not None:
+            out["status"] = 2
+            out["n_unstable"] = sum(not _stable(np.array(p[:2]), kT, a, b) for p in two)
+    if new is not None:
+        out["phases"] = new
+        out["polished"] = 1
+    else:
+        out["polished"] = 2
+    return out
+
+
+def _distinct_phases(raw):
+    """Step 6 classification: the search's phases merged greedily in their
+    order when their densities agree within MERGE_TOL (the merged density
+    being total particles over total volume), phases below VOLUME_MIN
+    dropped, the rest sorted by rho_A - rho_B."""
     groups = []  # [particles A, particles B, volume]
     for ra, rb, V in raw:
+        if not V > 0:
+            continue
         r = np.array([ra, rb])
         for g in groups:
             rg = np.array([g[0] / g[2], g[1] / g[2]])
@@ -350,34 +450,15 @@ def phase_point(NA: float, NB: float, kT, a, b, threshold=1e-12, max_iter=200000
             groups.append([ra * V, rb * V, V])
     ph = [(g[0] / g[2], g[1] / g[2], g[2]) for g in groups if g[2] >= VOLUME_MIN]
     ph.sort(key=lambda p: p[0] - p[1])
-    out["n_unstable"] = sum(not _stable(np.array(p[:2]), kT, a, b) for p in ph)
-    out["phases"] = ph
-    out["status"] = len(ph)
-    if len(ph) not in (2, 3):
-        return out
-    new = _polish(N, ph, kT, a, b)
-    if new is None and len(ph) == 3:
-        # a search stopped at its iteration cap can leave two nearly equal
-        # phases: merge the closest pair and polish as two phases
-        pairs = [(0, 1), (0, 2), (1, 2)]
-        i, j = min(pairs, key=lambda q: max(abs(ph[q[0]][0] - ph[q[1]][0]), abs(ph[q[0]][1] - ph[q[1]][1])))
-        k = 3 - i - j
-        V = ph[i][2] + ph[j][2]
-        m = ((ph[i][0] * ph[i][2] + ph[j][0] * ph[j][2]) / V, (ph[i][1] * ph[i][2] + ph[j][1] * ph[j][2]) / V, V)
-        two = sorted([m, ph[k]], key=lambda p: p[0] - p[1])
-        new = _polish(N, two, kT, a, b)
-        if new is not None:
-            out["status"] = 2
-            out["n_unstable"] = sum(not _stable(np.array(p[:2]), kT, a, b) for p in two)
-    if new is not None:
-        out["phases"] = new
-        out["polished"] = 1
-    else:
-        out["polished"] = 2
-    return out
+    return ph
 
 
-def _polish(N, ph, kT, a, b):
+def _distinct(p, q):
+    scale = max(1.0, abs(p[0]), abs(p[1]), abs(q[0]), abs(q[1]))
+    return max(abs(p[0] - q[0]), abs(p[1] - q[1])) > MERGE_TOL * scale
+
+
+def _polish(N, ph, F_search, kT, a, b):
     """Newton polish of 2 or 3 phases (see phase_point); None if rejected."""
     if len(ph) == 2:
         xa, xb, phi = coexistence_two_phase(N, ph[0][:2], ph[1][:2], kT, a, b)
@@ -387,9 +468,16 @@ def _polish(N, ph, kT, a, b):
         M = np.vstack([np.column_stack(rs), np.ones(3)])
         vol = np.linalg.solve(M, np.array([N[0], N[1], 1.0]))
         new = [(r[0], r[1], v) for r, v in zip(rs, vol)]
-    ok = all(np.isfinite(x) for p in new for x in p) and all(0 < p[2] < 1 for p in new)
-    ok = ok and max(max(abs(p[0] - q[0]), abs(p[1] - q[1])) for p, q in zip(new, ph)) <= POLISH_MAX
-    return new if ok else None
+    if not (all(np.isfinite(x) for p in new for x in p) and all(0 < p[2] < 1 for p in new)):
+        return None
+    if not all(_distinct(new[i], new[j]) for i in range(len(new)) for j in range(i + 1, len(new))):
+        return None
+    if not all(_stable(np.array(p[:2]), kT, a, b) for p in new):
+        return None
+    F_new = sum(p[2] * free_energy_density(np.array(p[:2]), kT, a, b) for p in new)
+    if not F_new <= F_search + F_SLACK * max(1.0, abs(F_search)):
+        return None
+    return new
 
 
 def coexistence_invariant_point(phases, kT, a, b, tol=1e-15, maxit=50):
