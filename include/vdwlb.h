@@ -126,7 +126,8 @@ vdwlb_status vdwlb_plan_destroy(vdwlb_plan* plan);
  * multiple of 64); a plane holds plane_elems * C elements. */
 int64_t vdwlb_plane_elems(const vdwlb_plan* plan);
 
-/* Bytes of one population buffer: 9 * C * plane_elems * sizeof(dtype).
+/* Bytes of one population buffer: Q * C * plane_elems * sizeof(dtype)
+ * (Q = 9 for D2Q9, 3 for D1Q3).
  * The caller allocates two (ping-pong).  0 for a NULL plan. */
 size_t vdwlb_state_bytes(const vdwlb_plan* plan);
 
@@ -192,6 +193,56 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* st
  * initialise tanh slabs with bulk values as in Sec. V.  Host-only.  Returns
  * VDWLB_E_INVALID_ARG when kT >= kT_cr or a, b, kT are not positive. */
 vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, double* rho_liquid);
+
+/* Phase diagram of a two-component mixture (Appendix A), one GPU thread per
+ * overall composition: point k holds NA[k] and NB[k] particles in a volume of 1.
+ *   - invalid (a density <= 0 or b . N >= 1): status -1, F = NaN, no phases;
+ *   - Hessian of the bulk free energy positive definite (Sec. VI.A): stable,
+ *     status 1, phases = {(NA, NB, 1)}, 0 iterations, no search;
+ *   - otherwise the direct search over three phases: phase 3 (fixed by
+ *     conservation) starts empty, phases 1 and 2 as halves displaced by
+ *     +-eps/2 along the unstable eigenvector d (d_A >= 0, eps = 0.05
+ *     min(NA, NB)); volumes 1/3 each, the empty phase shrunk to (1 - b.N)/2
+ *     when b.N > 1/3; empty components add nothing to the free energy
+ *     (rho ln rho -> 0); each iteration tries +step
+ *     then -step on A1, B1, V1, A2, B2, V2 and keeps the first strictly lowest
+ *     total free energy, else halves the step (initially 0.01); it stops when
+ *     the step falls below threshold or after max_iter iterations.  Then
+ *     phases whose densities agree within 1e-3 (relative to max(1, |rho|))
+ *     are merged, those with volume below 1e-6 dropped, the rest sorted by
+ *     rho_A - rho_B, and a Newton polish solves equal mu^c and p (with the
+ *     lever rule through N for two phases), accepted when its volumes lie in
+ *     (0, 1), its phases stay distinct and locally stable and its free energy
+ *     does not exceed the search's (by more than 1e-12 relative); a rejected
+ *     three-phase polish merges the closest pair and polishes two phases,
+ *     and failing that drops the smallest phase and polishes the other two.
+ *     Before the polish, while a distinct phase is unstable (at most twice),
+ *     the search starts again (step 6(b)) with the largest unstable phase
+ *     split along its unstable direction into phases 1 and 2 and phase 3
+ *     holding the other phases packed together.
+ *     The polish makes a point exact even when the search stopped at
+ *     max_iter before converging.  status = the number of distinct phases (1, 2, 3; 1 with
+ *     iterations > 0 means the search did not split), 0 if the search ended
+ *     with an infinite free energy.
+ *   kT, a (host, 2 x 2 row-major, symmetric), b (host, 2): the mixture of Sec. II.
+ *   n >= 0; NA, NB: device [n] doubles, read.
+ *   threshold > 0 (the paper uses 1e-12); 1 <= max_iter <= 7e8 iterations
+ *   per search.
+ *   phases  device [n][3][3] (rho_A, rho_B, V) of the distinct phases, unused
+ *           slots 0, written.
+ *   raw     device [n][3][3] the search's own three phases (zeros without a
+ *           search), written.
+ *   F       device [n]: total free energy at the end of the search (f(N) for
+ *           a stable point), written.
+ *   info    device int32 [n][4]: status, iterations (all searches), the number of distinct
+ *           phases whose Hessian is not positive definite (before the polish),
+ *           polish (0 none, 1 accepted, 2 rejected: search values kept), written.
+ * VDWLB_E_INVALID_ARG for kT or threshold not positive and finite, a not finite
+ * or not symmetric, b not positive, n < 0, max_iter < 1, or a NULL pointer when
+ * n > 0.  Asynchronous on stream. */
+vdwlb_status vdwlb_phase_points(double kT, const double* a, const double* b, int32_t n, const double* NA,
+                                const double* NB, double threshold, int32_t max_iter, double* phases, double* raw,
+                                double* F, int32_t* info, void* stream);
 
 /* Device-to-device copy of nbytes with a plain streaming kernel; used as the
  * bandwidth yardstick next to the sweep.  Asynchronous on stream. */

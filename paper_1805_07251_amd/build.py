@@ -34,7 +34,8 @@ FLAGS = [
     "-packed-fp32-ops",
 ]
 
-SOURCES = ["api.cpp", "runtime.hip", "sweep_f64.hip", "sweep_f32.hip", "batch.hip", "adjoint.hip", "diag.hip"]
+SOURCES = ["api.cpp", "runtime.hip", "sweep_f64.hip", "sweep_f32.hip", "batch.hip", "adjoint.hip", "diag.hip",
+           "phase.hip"]
 
 
 def _hipcc() -> str:

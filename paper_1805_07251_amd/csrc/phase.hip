@@ -1,0 +1,596 @@
+// Phase diagram of a two-component van der Waals mixture (Appendix A), one
+// GPU thread per overall composition (A, B) in a volume of 1:
+//   1. stability: the Hessian of the bulk free-energy density at (A, B)
+//      (Sec. VI.A); a positive-definite point is one stable phase, no search;
+//   2. direct search over three phases: phases 1 and 2 hold (A1, B1, V1) and
+//      (A2, B2, V2), phase 3 follows from conservation; every iteration tries
+//      each of the six variables moved by +step and by -step, takes the lowest
+//      total free energy if it improves and otherwise halves the step, until
+//      the step falls below the threshold;
+//   3. classification: the three phases merged when their densities agree,
+//      phases of negligible volume dropped, the rest sorted by rho_A - rho_B;
+//   4. polish: Newton on the coexistence conditions (equal mu^c and p of
+//      Sec. II, with the lever rule through (A, B) for two phases), so a
+//      binodal point comes out at round-off rather than at the search's
+//      resolution, and even where the search stopped at its iteration cap
+//      before converging: the search supplies the phase count and the start.
+//      A rejected three-phase polish merges the closest pair and polishes it
+//      as two phases, and failing that drops the smallest phase and polishes
+//      the other two.
+// Bulk free-energy density f = sum_c rho^c kT ln(rho^c / (1 - eta))
+// - sum_cc' a^{cc'} rho^c rho^c' (Eq. continuousFreeEnergy without gradients).
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/vdwlb.h"
+#include "internal.hpp"
+
+namespace vdwlb {
+namespace {
+
+constexpr int PH_BLOCK = 64;             // one wave per workgroup: waves finish independently
+constexpr int PH_RESTARTS = 2;           // restarts of step 6(b) per point
+constexpr int PH_MAX_ITER = 700000000;   // iterations of one search; (1 + PH_RESTARTS) of them fit an int32
+constexpr double MERGE_TOL = 1e-3;       // phases closer than this (max norm, relative to max(1, |rho|)) are one
+constexpr double VOLUME_MIN = 1e-6;      // merged phases with less volume are dropped
+constexpr double F_SLACK = 1e-12;        // a polish may not raise the free energy by more (relative to max(1, |F|))
+constexpr int NEWTON2_MAXIT = 100, NEWTON3_MAXIT = 50, DAMP_MAX = 64;
+constexpr double NEWTON2_TOL = 1e-14, NEWTON3_TOL = 1e-15;
+
+struct Mix {
+    double kT, a00, a01, a11, b0, b1;
+};
+
+struct Rho {
+    double a, b;
+};
+
+__device__ __forceinline__ bool admissible(const Mix& m, Rho r) {
+    return r.a > 0.0 && r.b > 0.0 && m.b0 * r.a + m.b1 * r.b < 1.0;
+}
+
+__device__ __forceinline__ double attraction(const Mix& m, Rho r) {
+    return (r.a * m.a00 + r.b * m.a01) * r.a + (r.a * m.a01 + r.b * m.a11) * r.b;
+}
+
+__device__ __forceinline__ double free_density(const Mix& m, Rho r) {
+    const double g = 1.0 - (m.b0 * r.a + m.b1 * r.b);
+    return (r.a * m.kT * log(r.a / g) + r.b * m.kT * log(r.b / g)) - attraction(m, r);
+}
+
+// V f(A/V, B/V) of one phase, f extended to empty components
+// (rho ln rho -> 0): negative amounts and particles without volume are
+// infinitely expensive, an empty phase of zero volume costs nothing.
+__device__ __forceinline__ double phase_energy(const Mix& m, double A, double B, double V) {
+    if (!(V >= 0.0) || !(A >= 0.0) || !(B >= 0.0)) return INFINITY;
+    if (V == 0.0) return (A == 0.0 && B == 0.0) ? 0.0 : INFINITY;
+    const Rho r{A / V, B / V};
+    const double g = 1.0 - (m.b0 * r.a + m.b1 * r.b);
+    if (!(g > 0.0)) return INFINITY;
+    const double ea = r.a > 0.0 ? r.a * m.kT * log(r.a / g) : 0.0;
+    const double eb = r.b > 0.0 ? r.b * m.kT * log(r.b / g) : 0.0;
+    return V * ((ea + eb) - attraction(m, r));
+}
+
+struct Sym2 {
+    double xx, xy, yy;
+};
+
+// Hessian d^2 f / d rho^c d rho^c'
+__device__ __forceinline__ Sym2 hessian(const Mix& m, Rho r) {
+    const double g = 1.0 - (m.b0 * r.a + m.b1 * r.b), ig = 1.0 / g, t = (r.a + r.b) * ig * ig;
+    Sym2 h;
+    h.xx = m.kT * (1.0 / r.a + 2.0 * m.b0 * ig + m.b0 * m.b0 * t) - 2.0 * m.a00;
+    h.xy = m.kT * ((m.b0 + m.b1) * ig + m.b0 * m.b1 * t) - 2.0 * m.a01;
+    h.yy = m.kT * (1.0 / r.b + 2.0 * m.b1 * ig + m.b1 * m.b1 * t) - 2.0 * m.a11;
+    return h;
+}
+
+__device__ __forceinline__ bool stable(const Mix& m, Rho r) {
+    const Sym2 h = hessian(m, r);
+    return h.xx > 0.0 && h.xx * h.yy - h.xy * h.xy > 0.0;
+}
+
+// full bulk chemical potentials (with the constant kT) and pressure
+__device__ __forceinline__ void mu_p(const Mix& m, Rho r, double& mua, double& mub, double& p) {
+    const double g = 1.0 - (m.b0 * r.a + m.b1 * r.b), tot = r.a + r.b;
+    mua = m.kT * (log(r.a / g) + 1.0 + m.b0 * tot / g) - 2.0 * (m.a00 * r.a + m.a01 * r.b);
+    mub = m.kT * (log(r.b / g) + 1.0 + m.b1 * tot / g) - 2.0 * (m.a01 * r.a + m.a11 * r.b);
+    p = tot * m.kT / g - attraction(m, r);
+}
+
+// Unit eigenvector of the lowest eigenvalue, sign fixed by d.a >= 0 (d.b > 0
+// when d.a = 0).
+__device__ __forceinline__ Rho unstable_direction(Sym2 h) {
+    Rho d;
+    if (h.xy == 0.0) {
+        d = h.xx <= h.yy ? Rho{1.0, 0.0} : Rho{0.0, 1.0};
+    } else {
+        const double hd = 0.5 * (h.xx - h.yy);
+        const double lam = 0.5 * (h.xx + h.yy) - sqrt(hd * hd + h.xy * h.xy);
+        const Rho v1{h.xy, lam - h.xx}, v2{lam - h.yy, h.xy};
+        const double n1 = v1.a * v1.a + v1.b * v1.b, n2 = v2.a * v2.a + v2.b * v2.b;
+        d = n1 >= n2 ? v1 : v2;
+        const double in = 1.0 / sqrt(n1 >= n2 ? n1 : n2);
+        d.a *= in;
+        d.b *= in;
+    }
+    if (d.a < 0.0 || (d.a == 0.0 && d.b < 0.0)) {
+        d.a = -d.a;
+        d.b = -d.b;
+    }
+    return d;
+}
+
+// Solve A x = r in place (x returned in r) by Gaussian elimination with
+// partial pivoting; every index is a compile-time constant so A stays in
+// registers.  Returns false for a singular matrix.
+template <int N>
+__device__ __forceinline__ bool solve(double (&A)[N][N], double (&r)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            if (fabs(A[i][k]) > fabs(A[k][k])) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const double t = A[i][j];
+                    A[i][j] = A[k][j];
+                    A[k][j] = t;
+                }
+                const double t = r[i];
+                r[i] = r[k];
+                r[k] = t;
+            }
+        }
+        if (!(A[k][k] != 0.0)) return false;
+        const double ip = 1.0 / A[k][k];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const double f = A[i][k] * ip;
+#pragma unroll
+            for (int j = k; j < N; ++j) A[i][j] -= f * A[k][j];
+            r[i] -= f * r[k];
+        }
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        double acc = r[k];
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) acc -= A[k][j] * r[j];
+        r[k] = acc / A[k][k];
+    }
+    return true;
+}
+
+struct Phase {
+    double a, b, v;  // densities and volume
+};
+
+// Two phases of overall composition N: Newton on mu(x) = mu(y), p(x) = p(y)
+// and phi x + (1 - phi) y = N (analytic Jacobian: d mu / d rho = H,
+// d p / d rho = rho^T H by Gibbs-Duhem).
+__device__ bool polish2(const Mix& m, Rho N, Phase& P0, Phase& P1) {
+    double z[5] = {P0.a, P0.b, P1.a, P1.b, 0.0};
+    const double da = P0.a - P1.a, db = P0.b - P1.b;
+    z[4] = ((N.a - P1.a) * da + (N.b - P1.b) * db) / (da * da + db * db);
+    for (int it = 0; it < NEWTON2_MAXIT; ++it) {
+        const Rho x{z[0], z[1]}, y{z[2], z[3]};
+        const double phi = z[4];
+        double mxa, mxb, px, mya, myb, py;
+        mu_p(m, x, mxa, mxb, px);
+        mu_p(m, y, mya, myb, py);
+        double r[5] = {mxa - mya, mxb - myb, px - py, phi * x.a + (1.0 - phi) * y.a - N.a,
+                       phi * x.b + (1.0 - phi) * y.b - N.b};
+        const Sym2 hx = hessian(m, x), hy = hessian(m, y);
+        double J[5][5] = {
+            {hx.xx, hx.xy, -hy.xx, -hy.xy, 0.0},
+            {hx.xy, hx.yy, -hy.xy, -hy.yy, 0.0},
+            {x.a * hx.xx + x.b * hx.xy, x.a * hx.xy + x.b * hx.yy, -(y.a * hy.xx + y.b * hy.xy),
+             -(y.a * hy.xy + y.b * hy.yy), 0.0},
+            {phi, 0.0, 1.0 - phi, 0.0, x.a - y.a},
+            {0.0, phi, 0.0, 1.0 - phi, x.b - y.b},
+        };
+        if (!solve<5>(J, r)) return false;
+        double lam = 1.0, t[5];
+        int k = 0;
+        for (; k < DAMP_MAX; ++k) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) t[i] = z[i] - lam * r[i];
+            if (admissible(m, Rho{t[0], t[1]}) && admissible(m, Rho{t[2], t[3]})) break;
+            lam *= 0.5;
+        }
+        if (k == DAMP_MAX) return false;
+        double smax = 0.0, zmax = 1.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            z[i] = t[i];
+            smax = fmax(smax, fabs(lam * r[i]));
+            zmax = fmax(zmax, fabs(z[i]));
+        }
+        if (smax < NEWTON2_TOL * zmax) break;
+    }
+    P0 = Phase{z[0], z[1], z[4]};
+    P1 = Phase{z[2], z[3], 1.0 - z[4]};
+    return true;
+}
+
+// Three phases: Newton on equal mu^c and p in all three (no free variable at
+// fixed temperature), then the volumes from the lever rule.
+__device__ bool polish3(const Mix& m, Rho N, Phase (&P)[3]) {
+    double z[6] = {P[0].a, P[0].b, P[1].a, P[1].b, P[2].a, P[2].b};
+    for (int it = 0; it < NEWTON3_MAXIT; ++it) {
+        const Rho r0{z[0], z[1]}, r1{z[2], z[3]}, r2{z[4], z[5]};
+        double m0a, m0b, p0, m1a, m1b, p1, m2a, m2b, p2;
+        mu_p(m, r0, m0a, m0b, p0);
+        mu_p(m, r1, m1a, m1b, p1);
+        mu_p(m, r2, m2a, m2b, p2);
+        double r[6] = {m0a - m1a, m0b - m1b, m0a - m2a, m0b - m2b, p0 - p1, p0 - p2};
+        const Sym2 h0 = hessian(m, r0), h1 = hessian(m, r1), h2 = hessian(m, r2);
+        const double g0a = r0.a * h0.xx + r0.b * h0.xy, g0b = r0.a * h0.xy + r0.b * h0.yy;
+        const double g1a = r1.a * h1.xx + r1.b * h1.xy, g1b = r1.a * h1.xy + r1.b * h1.yy;
+        const double g2a = r2.a * h2.xx + r2.b * h2.xy, g2b = r2.a * h2.xy + r2.b * h2.yy;
+        double J[6][6] = {
+            {h0.xx, h0.xy, -h1.xx, -h1.xy, 0.0, 0.0}, {h0.xy, h0.yy, -h1.xy, -h1.yy, 0.0, 0.0},
+            {h0.xx, h0.xy, 0.0, 0.0, -h2.xx, -h2.xy}, {h0.xy, h0.yy, 0.0, 0.0, -h2.xy, -h2.yy},
+            {g0a, g0b, -g1a, -g1b, 0.0, 0.0},         {g0a, g0b, 0.0, 0.0, -g2a, -g2b},
+        };
+        if (!solve<6>(J, r)) return false;
+        double lam = 1.0, t[6];
+        int k = 0;
+        for (; k < DAMP_MAX; ++k) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] = z[i] - lam * r[i];
+            if (admissible(m, Rho{t[0], t[1]}) && admissible(m, Rho{t[2], t[3]}) && admissible(m, Rho{t[4], t[5]}))
+                break;
+            lam *= 0.5;
+        }
+        if (k == DAMP_MAX) return false;
+        double smax = 0.0, zmax = 1.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            z[i] = t[i];
+            smax = fmax(smax, fabs(lam * r[i]));
+            zmax = fmax(zmax, fabs(z[i]));
+        }
+        if (smax < NEWTON3_TOL * zmax) break;
+    }
+    double M[3][3] = {{z[0], z[2], z[4]}, {z[1], z[3], z[5]}, {1.0, 1.0, 1.0}};
+    double v[3] = {N.a, N.b, 1.0};
+    if (!solve<3>(M, v)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[i] = Phase{z[2 * i], z[2 * i + 1], v[i]};
+    return true;
+}
+
+__device__ __forceinline__ bool finite_phase(const Phase& p) {
+    return isfinite(p.a) && isfinite(p.b) && isfinite(p.v);
+}
+
+__device__ __forceinline__ bool distinct(const Phase& p, const Phase& q) {
+    const double scale = fmax(fmax(1.0, fmax(fabs(p.a), fabs(p.b))), fmax(fabs(q.a), fabs(q.b)));
+    return fmax(fabs(p.a - q.a), fabs(p.b - q.b)) > MERGE_TOL * scale;
+}
+
+// Polish of n = 2 or 3 sorted distinct phases in place.  Accepted when the
+// result is finite with volumes in (0, 1), its phases stay distinct (the
+// equations also have the trivial root of equal phases), each phase is
+// locally stable, and its free energy does not exceed the search's F_search
+// by more than F_SLACK; otherwise false and P untouched.
+__device__ bool polish(const Mix& m, Rho N, double F_search, Phase (&P)[3], int n) {
+    Phase Q[3] = {P[0], P[1], P[2]};
+    const bool ok = n == 2 ? polish2(m, N, Q[0], Q[1]) : polish3(m, N, Q);
+    if (!ok) return false;
+    double F = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!finite_phase(Q[i]) || !(Q[i].v > 0.0 && Q[i].v < 1.0)) return false;
+        for (int j = i + 1; j < n; ++j)
+            if (!distinct(Q[i], Q[j])) return false;
+        if (!stable(m, Rho{Q[i].a, Q[i].b})) return false;
+        F += Q[i].v * free_density(m, Rho{Q[i].a, Q[i].b});
+    }
+    if (!(F <= F_search + F_SLACK * fmax(1.0, fabs(F_search)))) return false;
+    for (int i = 0; i < n; ++i) P[i] = Q[i];
+    return true;
+}
+
+__device__ __forceinline__ void sort_phases(Phase (&P)[3], int n) {
+    // insertion sort by rho_A - rho_B (n <= 3)
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && (P[j].a - P[j].b) < (P[j - 1].a - P[j - 1].b); --j) {
+            const Phase t = P[j];
+            P[j] = P[j - 1];
+            P[j - 1] = t;
+        }
+}
+
+__device__ __forceinline__ int count_unstable(const Mix& m, const Phase (&P)[3], int n) {
+    int u = 0;
+    for (int i = 0; i < n; ++i) u += stable(m, Rho{P[i].a, P[i].b}) ? 0 : 1;
+    return u;
+}
+
+// Status codes between the kernels: the public ones (-1 invalid, 0 failed,
+// 1..3 phases) are final; the others mark work still to do.
+constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_RESTART = 5, ST_STABLE_PENDING = 6;
+
+// The direct search from the amounts z = (A1, B1, V1, A2, B2, V2), phase 3
+// holding the rest of N.  Returns the final total free energy and adds the
+// iterations to iters.
+__device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double threshold, int max_iter, int& iters) {
+    double e1 = phase_energy(m, z[0], z[1], z[2]);
+    double e2 = phase_energy(m, z[3], z[4], z[5]);
+    double e3 = phase_energy(m, N.a - z[0] - z[3], N.b - z[1] - z[4], 1.0 - z[2] - z[5]);
+    double F = (e1 + e2) + e3;
+    double step = 0.01;
+    for (int it = 0; it < max_iter; ++it) {
+        ++iters;
+        double best = F, b1 = e1, b2 = e2, b3 = e3;
+        int bk = -1;
+        double bs = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const double mv = s == 0 ? step : -step;
+                double t[6] = {z[0], z[1], z[2], z[3], z[4], z[5]};
+                t[k] += mv;
+                const double t1 = k < 3 ? phase_energy(m, t[0], t[1], t[2]) : e1;
+                const double t2 = k < 3 ? e2 : phase_energy(m, t[3], t[4], t[5]);
+                const double t3 = phase_energy(m, N.a - t[0] - t[3], N.b - t[1] - t[4], 1.0 - t[2] - t[5]);
+                const double Ft = (t1 + t2) + t3;
+                if (Ft < best) {
+                    best = Ft;
+                    bk = k;
+                    bs = mv;
+                    b1 = t1;
+                    b2 = t2;
+                    b3 = t3;
+                }
+            }
+        }
+        if (bk >= 0 && F - best > 0.0) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                if (j == bk) z[j] += bs;
+            F = best;
+            e1 = b1;
+            e2 = b2;
+            e3 = b3;
+        } else {
+            step *= 0.5;
+            if (step < threshold) break;
+        }
+    }
+    return F;
+}
+
+// Steps 1 and 2: stability test and direct search.  First pass (restart = 0):
+// every point; writes the search's three phases (rho_A, rho_B, V) to raw,
+// its free energy to F and (status, iterations) to info[0..1].  Restart
+// passes: only points marked ST_RESTART, whose start amounts the classify
+// kernel left in raw[0..5]; iterations accumulate.
+__global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const double* __restrict__ NA,
+                                                          const double* __restrict__ NB, double threshold,
+                                                          int max_iter, int restart, double* __restrict__ raw,
+                                                          double* __restrict__ Fout, int* __restrict__ info) {
+    const int i = blockIdx.x * PH_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const Rho N{NA[i], NB[i]};
+    double* w = raw + (int64_t)i * 9;
+    double F = NAN;
+    int status = ST_INVALID, iters = 0;
+    double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (restart) {
+        if (info[(int64_t)i * 4 + 0] != ST_RESTART) return;
+        iters = info[(int64_t)i * 4 + 1];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) z[k] = w[k];
+        F = direct_search(m, N, z, threshold, max_iter, iters);
+        status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
+    } else if (admissible(m, N)) {
+        F = free_density(m, N);
+        const Sym2 h = hessian(m, N);
+        if (h.xx > 0.0 && h.xx * h.yy - h.xy * h.xy > 0.0) {
+            status = ST_STABLE_PENDING;
+        } else {
+            // start: phase 3 empty; phases 1 and 2 split along the unstable
+            // direction, phase 2 holding exactly what phase 1 does not; volumes
+            // 1/3 each, the empty phase shrunk to (1 - eta_N)/2 above eta_N = 1/3
+            // so that phases 1 and 2 stay below the excluded-volume limit
+            const Rho d = unstable_direction(h);
+            const double eps = 0.05 * fmin(N.a, N.b);
+            const double V3 = fmin(1.0 / 3.0, 0.5 * (1.0 - (m.b0 * N.a + m.b1 * N.b)));
+            const double V12 = 0.5 * (1.0 - V3);
+            z[0] = 0.5 * N.a + 0.5 * eps * d.a;
+            z[1] = 0.5 * N.b + 0.5 * eps * d.b;
+            z[2] = V12;
+            z[3] = N.a - z[0];
+            z[4] = N.b - z[1];
+            z[5] = V12;
+            F = direct_search(m, N, z, threshold, max_iter, iters);
+            status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
+        }
+    }
+    if (status == ST_SEARCHED || status == ST_FAILED) {
+        // a phase of zero volume is reported with zero densities
+        const double A3 = N.a - z[0] - z[3], B3 = N.b - z[1] - z[4], V3 = 1.0 - z[2] - z[5];
+        const double q[9] = {z[0], z[1], z[2], z[3], z[4], z[5], A3, B3, V3};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double V = q[3 * k + 2];
+            w[3 * k + 0] = V > 0.0 ? q[3 * k + 0] / V : 0.0;
+            w[3 * k + 1] = V > 0.0 ? q[3 * k + 1] / V : 0.0;
+            w[3 * k + 2] = V;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) w[q] = 0.0;
+    }
+    Fout[i] = F;
+    info[(int64_t)i * 4 + 0] = status;
+    info[(int64_t)i * 4 + 1] = iters;
+}
+
+// Steps 3 and 4: classification and polish of the searched points, with the
+// restart of step 6(b): while restarts_left > 0, a point whose distinct
+// phases include an unstable one is sent back to the search (ST_RESTART)
+// with that phase (the largest unstable one) split along its unstable
+// direction into phases 1 and 2, and phase 3 holding the others packed
+// together; the start amounts go to raw[0..5].  Otherwise writes phases and
+// completes info (final status, -, n_unstable, polished).  Points finished
+// in an earlier pass are left alone.
+__global__ void __launch_bounds__(PH_BLOCK) k_phase_classify(Mix m, int n, const double* __restrict__ NA,
+                                                            const double* __restrict__ NB, int restarts_left,
+                                                            double* __restrict__ raw,
+                                                            const double* __restrict__ Fs,
+                                                            double* __restrict__ phases, int* __restrict__ info) {
+    const int i = blockIdx.x * PH_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const Rho N{NA[i], NB[i]};
+    Phase P[3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    int status = info[(int64_t)i * 4 + 0], unstable_n = 0, polished = 0;
+    if (status >= 1 && status <= 3) return;
+    if (status == ST_STABLE_PENDING) {
+        status = 1;
+        P[0] = Phase{N.a, N.b, 1.0};
+    } else if (status == ST_SEARCHED) {
+        double* w = raw + (int64_t)i * 9;
+        const Phase R[3] = {{w[0], w[1], w[2]}, {w[3], w[4], w[5]}, {w[6], w[7], w[8]}};
+        // merge greedily in search order (particles and volumes add)
+        double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gV[3] = {0.0, 0.0, 0.0};
+        int ng = 0;
+        for (int q = 0; q < 3; ++q) {
+            if (!(R[q].v > 0.0)) continue;
+            int hit = -1;
+            for (int g = 0; g < ng && hit < 0; ++g) {
+                const double ra = gA[g] / gV[g], rb = gB[g] / gV[g];
+                const double scale = fmax(1.0, fmax(fabs(ra), fabs(rb)));
+                if (fmax(fabs(R[q].a - ra), fabs(R[q].b - rb)) <= MERGE_TOL * scale) hit = g;
+            }
+            if (hit < 0) hit = ng++;
+            gA[hit] += R[q].a * R[q].v;
+            gB[hit] += R[q].b * R[q].v;
+            gV[hit] += R[q].v;
+        }
+        int np = 0;
+        for (int g = 0; g < ng; ++g)
+            if (gV[g] >= VOLUME_MIN) P[np++] = Phase{gA[g] / gV[g], gB[g] / gV[g], gV[g]};
+        sort_phases(P, np);
+        status = np;
+        unstable_n = count_unstable(m, P, np);
+        if (restarts_left > 0 && unstable_n > 0) {
+            int u = -1;
+            for (int q = 0; q < np; ++q)
+                if (!stable(m, Rho{P[q].a, P[q].b}) && (u < 0 || P[q].v > P[u].v)) u = q;
+            const double Au = P[u].a * P[u].v, Bu = P[u].b * P[u].v, Vu = P[u].v;
+            const Rho d = unstable_direction(hessian(m, Rho{P[u].a, P[u].b}));
+            const double eps = 0.05 * fmin(Au, Bu);
+            const double A1 = 0.5 * Au + 0.5 * eps * d.a, B1 = 0.5 * Bu + 0.5 * eps * d.b;
+            w[0] = A1;
+            w[1] = B1;
+            w[2] = 0.5 * Vu;
+            w[3] = Au - A1;
+            w[4] = Bu - B1;
+            w[5] = 0.5 * Vu;
+            info[(int64_t)i * 4 + 0] = ST_RESTART;
+            return;
+        }
+        if (np == 2 || np == 3) {
+            if (polish(m, N, Fs[i], P, np)) {
+                polished = 1;
+            } else if (np == 3) {
+                // merge the closest pair and polish the two phases
+                auto dist = [&](int u, int w2) { return fmax(fabs(P[u].a - P[w2].a), fabs(P[u].b - P[w2].b)); };
+                int u = 0, v = 1;
+                double dm = dist(0, 1);
+                if (dist(0, 2) < dm) {
+                    u = 0;
+                    v = 2;
+                    dm = dist(0, 2);
+                }
+                if (dist(1, 2) < dm) {
+                    u = 1;
+                    v = 2;
+                }
+                const int o = 3 - u - v;
+                const double V = P[u].v + P[v].v;
+                Phase two[3] = {Phase{(P[u].a * P[u].v + P[v].a * P[v].v) / V, (P[u].b * P[u].v + P[v].b * P[v].v) / V, V},
+                                P[o], Phase{0.0, 0.0, 0.0}};
+                sort_phases(two, 2);
+                int u2 = count_unstable(m, two, 2);
+                bool ok = polish(m, N, Fs[i], two, 2);
+                if (!ok) {
+                    // or the smallest phase is a seed the search left behind: drop it
+                    int k = 0;
+                    if (P[1].v < P[k].v) k = 1;
+                    if (P[2].v < P[k].v) k = 2;
+                    two[0] = P[k == 0 ? 1 : 0];
+                    two[1] = P[k == 2 ? 1 : 2];
+                    u2 = count_unstable(m, two, 2);
+                    ok = polish(m, N, Fs[i], two, 2);
+                }
+                if (ok) {
+                    polished = 1;
+                    status = 2;
+                    unstable_n = u2;
+                    P[0] = two[0];
+                    P[1] = two[1];
+                    P[2] = Phase{0.0, 0.0, 0.0};
+                } else {
+                    polished = 2;
+                }
+            } else {
+                polished = 2;
+            }
+        }
+    }
+    double* o = phases + (int64_t)i * 9;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const bool used = q < status;
+        o[3 * q + 0] = used ? P[q].a : 0.0;
+        o[3 * q + 1] = used ? P[q].b : 0.0;
+        o[3 * q + 2] = used ? P[q].v : 0.0;
+    }
+    info[(int64_t)i * 4 + 0] = status;
+    info[(int64_t)i * 4 + 2] = unstable_n;
+    info[(int64_t)i * 4 + 3] = polished;
+}
+
+bool finite_host(double x) { return x == x && x - x == 0.0; }
+
+}  // namespace
+}  // namespace vdwlb
+
+using namespace vdwlb;
+
+extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const double* b, int32_t n, const double* NA,
+                                           const double* NB, double threshold, int32_t max_iter, double* phases,
+                                           double* raw, double* F, int32_t* info, void* stream) {
+    if (!a || !b || n < 0) return VDWLB_E_INVALID_ARG;
+    if (!(kT > 0.0) || !finite_host(kT) || !(threshold > 0.0) || !finite_host(threshold) || max_iter < 1 ||
+        max_iter > PH_MAX_ITER)
+        return VDWLB_E_INVALID_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (!finite_host(a[k])) return VDWLB_E_INVALID_ARG;
+    if (a[1] != a[2]) return VDWLB_E_INVALID_ARG;
+    for (int k = 0; k < 2; ++k)
+        if (!(b[k] > 0.0) || !finite_host(b[k])) return VDWLB_E_INVALID_ARG;
+    if (n == 0) return VDWLB_OK;
+    if (!NA || !NB || !phases || !raw || !F || !info) return VDWLB_E_INVALID_ARG;
+    const Mix m{kT, a[0], a[1], a[3], b[0], b[1]};
+    const unsigned nb = (unsigned)((n + PH_BLOCK - 1) / PH_BLOCK);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    for (int pass = 0; pass <= PH_RESTARTS && e == hipSuccess; ++pass) {
+        hipLaunchKernelGGL(k_phase_search, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold,
+                           (int)max_iter, pass, raw, F, (int*)info);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_phase_classify, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, PH_RESTARTS - pass,
+                           raw, (const double*)F, phases, (int*)info);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "phase-point kernels");
+}

@@ -97,3 +97,32 @@ def test_dimension_rules():
     assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
     d, keep = _desc(dim=3)
     assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
+
+
+def test_phase_points_validates_on_the_host():
+    """vdwlb_phase_points rejects bad mixture or search arguments before any
+    device call, and an empty point list is a no-op (no kernel launch)."""
+    import ctypes
+
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = np.array([0.45, 0.225, 0.225, 0.45])
+    b = np.array([1 / 3, 1 / 3])
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below returns on the host
+
+    def call(kT=1 / 3, a=a, b=b, n=1, thr=1e-12, it=1000, ptr=fake):
+        return V.lib().vdwlb_phase_points(kT, a.ctypes.data_as(dp), b.ctypes.data_as(dp), n, ptr, ptr, thr, it,
+                                          ptr, ptr, ptr, ptr, None)
+
+    assert call(n=0) == V.OK
+    assert call(n=0, ptr=None) == V.OK
+    assert call(ptr=None) == V.E_INVALID_ARG
+    assert call(kT=0.0) == V.E_INVALID_ARG
+    assert call(kT=float("nan")) == V.E_INVALID_ARG
+    assert call(thr=0.0) == V.E_INVALID_ARG
+    assert call(it=0) == V.E_INVALID_ARG
+    assert call(n=-1) == V.E_INVALID_ARG
+    assert call(a=np.array([0.45, 0.2, 0.225, 0.45])) == V.E_INVALID_ARG
+    assert call(a=np.array([0.45, np.inf, np.inf, 0.45])) == V.E_INVALID_ARG
+    assert call(b=np.array([1 / 3, 0.0])) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_phase_points(1 / 3, None, b.ctypes.data_as(dp), 0, None, None, 1e-12, 10, None, None, None,
+                                      None, None) == V.E_INVALID_ARG

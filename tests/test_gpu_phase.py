@@ -1,0 +1,153 @@
+"""GPU tests of the Appendix A phase-diagram pipeline (vdwlb_phase_points):
+per-point parity with the oracle's phase_point, the closed form of two
+identical components over a whole grid, and properties every polished point
+must have (conservation, equal mu^c and p, the unique three-phase point)."""
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KT = 1 / 3
+
+
+@pytest.fixture(scope="module")
+def phase():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import phase
+
+    return phase
+
+
+def host(res):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items() if k != "_keep"}
+
+
+def baseline():
+    """The Type III-H baseline mixture of Fig. graphBaselineCase (nu = 0.5)."""
+    return T.two_component_params(0.4, 0.4, 1.0, 0.5)
+
+
+@pytest.fixture(scope="module")
+def oracle_points():
+    """The oracle pipeline at a three-phase, two two-phase, two stable and one
+    invalid point of the baseline mixture (about 20 s of CPU)."""
+    a, b = baseline()
+    pts = [(0.8, 0.8), (2.0, 0.5), (0.5, 2.0), (0.3, 0.3), (0.05, 0.05), (2.0, 1.5)]
+    return pts, [T.phase_point(NA, NB, KT, a, b) for NA, NB in pts]
+
+
+def test_points_against_oracle(phase, oracle_points):
+    """Same status and polish outcome; polished phases equal to 1e-10 (both
+    sides solve the same coexistence equations to round-off); the raw
+    searches agree to the search's resolution (1e-5 on densities, 1e-9 on
+    the free energy): their decisions can part where two trial energies tie
+    within rounding, since the logarithms differ in the last bits."""
+    pts, want = oracle_points
+    a, b = baseline()
+    NA, NB = zip(*pts)
+    got = host(phase.phase_points(KT, a, b, NA, NB))
+    for k, (p, w) in enumerate(zip(pts, want)):
+        assert got["status"][k] == w["status"], p
+        assert got["polished"][k] == w["polished"], p
+        assert got["n_unstable"][k] == w["n_unstable"], p
+        ns = max(w["status"], 0)
+        gp = got["phases"][k][:ns]
+        wp = np.array(w["phases"]).reshape(-1, 3)[:ns]
+        np.testing.assert_allclose(gp, wp, rtol=0, atol=1e-10, err_msg=str(p))
+        assert np.all(got["phases"][k][ns:] == 0)
+        if w["status"] == -1:
+            assert np.isnan(got["F"][k]) and got["iterations"][k] == 0
+            continue
+        if w["iterations"] == 0:
+            assert got["iterations"][k] == 0 and got["F"][k] == pytest.approx(w["F"], rel=1e-14)
+            continue
+        assert got["F"][k] == pytest.approx(w["F"], rel=1e-9), p
+        # raw searches: compare the distinct phases they imply (the volume split
+        # between two copies of one phase is a flat direction of the search)
+        assert got["iterations"][k] < 200000 and w["iterations"] < 200000
+        raw_w = np.array(w["raw"])
+        raw_g = got["raw"][k]
+        for ra, rb, V in raw_g:
+            d = np.abs(raw_w[:, :2] - [ra, rb]).max(axis=1)
+            assert d.min() < 1e-5 or V < 1e-6, (p, ra, rb, V)
+
+
+def test_identical_components_grid(phase):
+    """Two identical components, nu = 1 (Fig. graphTwoIdenticalComponents):
+    every split point separates into a gas and a liquid of its own
+    composition at the pure fluid's Maxwell densities (tie lines through the
+    origin); no point has three phases; stable points are exactly those
+    with a positive-definite Hessian."""
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 1.0)
+    gas, liq = T.maxwell_single(a[0, 0], b[0], KT)
+    NA, NB = phase.composition_grid(b, 24)
+    got = host(phase.phase_points(KT, a, b, NA, NB))
+    st = got["status"]
+    pd = np.array([np.all(np.linalg.eigvalsh(T.hessian(np.array([x, y]), KT, a, b)) > 0) for x, y in zip(NA, NB)])
+    assert np.all((got["iterations"] == 0) == pd) and np.all(st[pd] == 1)
+    split = st == 2
+    assert np.array_equal(split, ~pd) and split.sum() >= 20
+    assert np.all(got["polished"][split] == 1)
+    for k in np.flatnonzero(split):
+        (ga, gb, vg), (la, lb, vl) = sorted(got["phases"][k][:2].tolist(), key=lambda p: p[0] + p[1])
+        x = NA[k] / (NA[k] + NB[k])
+        np.testing.assert_allclose([ga + gb, la + lb], [gas, liq], rtol=1e-10)
+        np.testing.assert_allclose([ga / (ga + gb), la / (la + lb)], [x, x], rtol=1e-10)
+        np.testing.assert_allclose([vg * ga + vl * la, vg * gb + vl * lb], [NA[k], NB[k]], rtol=1e-11)
+
+
+def test_baseline_grid_properties(phase, oracle_points):
+    """The baseline mixture over a 28 x 28 grid below the excluded-volume
+    line: every polished point conserves both species and the volume, has
+    equal mu^c and p in all its phases, lowers the free energy below the
+    homogeneous one, and has locally stable phases; every three-phase point
+    is the mixture's unique three-phase state (the oracle's, polished from
+    its own search)."""
+    a, b = baseline()
+    pts, want = oracle_points
+    three = np.array(want[0]["phases"])[:, :2]
+    NA, NB = phase.composition_grid(b, 28)
+    got = host(phase.phase_points(KT, a, b, NA, NB))
+    st, pol = got["status"], got["polished"]
+    assert not np.any(st <= 0)
+    pd = np.array([np.all(np.linalg.eigvalsh(T.hessian(np.array([x, y]), KT, a, b)) > 0) for x, y in zip(NA, NB)])
+    assert np.all((got["iterations"] == 0) == pd)
+    searched = ~pd
+    assert searched.sum() >= 50
+    assert np.count_nonzero(st[searched] == 3) >= 3
+    # the polish is accepted everywhere the search split the point
+    assert np.all(pol[st >= 2] == 1)
+    for k in np.flatnonzero(st >= 2):
+        ph = got["phases"][k][: st[k]]
+        N = np.array([NA[k], NB[k]])
+        np.testing.assert_allclose((ph[:, 2:3] * ph[:, :2]).sum(0), N, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(ph[:, 2].sum(), 1.0, rtol=1e-13)
+        mus = np.array([T.chemical_potential(r, KT, a, b) for r in ph[:, :2]])
+        ps = np.array([T.pressure(r, KT, a, b) for r in ph[:, :2]])
+        assert np.ptp(mus, axis=0).max() < 1e-11 and np.ptp(ps) < 1e-11, (N, ph)
+        assert got["F"][k] < T.free_energy_density(N, KT, a, b)
+        for r in ph[:, :2]:
+            assert np.all(np.linalg.eigvalsh(T.hessian(r, KT, a, b)) > 0), (N, r)
+        if st[k] == 3:
+            np.testing.assert_allclose(ph[:, :2], three, rtol=0, atol=1e-10)
+
+
+def test_iteration_cap_and_invalid_points(phase):
+    """max_iter = 1 stops every search (and restart) after one iteration and still returns
+    a classified result; invalid compositions give status -1 and no phases;
+    an empty list is a no-op."""
+    a, b = baseline()
+    NA = np.array([0.8, 2.0, 0.0, 2.0, -0.1, np.nan])
+    NB = np.array([0.8, 0.5, 0.5, 1.5, 0.3, 0.3])
+    got = host(phase.phase_points(KT, a, b, NA, NB, max_iter=1))
+    assert np.all((got["iterations"][:2] >= 1) & (got["iterations"][:2] <= 3))  # up to two restarts
+    assert np.all(got["status"][:2] >= 1)
+    assert list(got["status"][2:]) == [-1, -1, -1, -1]
+    assert np.all(got["phases"][2:] == 0) and np.all(np.isnan(got["F"][2:]))
+    empty = phase.phase_points(KT, a, b, np.zeros(0), np.zeros(0))
+    assert empty["phases"].shape == (0, 3, 3)
