@@ -13,8 +13,11 @@ cpu_baseline  the CPU oracle on the host, a bounded sample of the same workload.
 extra      the headline's median over 5 separate runs, with init, readback and
            host copies timed on their own; FP32 and 4-component sweeps; the
            batched phase-diagram workload in D2Q9 (strips through L2/MALL) and
-           D1Q3 (instances resident in LDS); a 2^24-site D1Q3 line; and the
-           adjoint against the plain forward.
+           D1Q3 (instances resident in LDS); a 2^24-site D1Q3 line; the
+           adjoint against the plain forward; the Appendix A phase diagram on
+           a 256 x 256 composition grid; and the verification workload
+           (phase-diagram points run as D1Q3 slabs, bulk states against the
+           binodal).
 """
 from __future__ import annotations
 
@@ -387,6 +390,62 @@ def adjoint_leg(seed):
     }
 
 
+def phase_diagram_leg(n=256, max_iter=200000):
+    """Appendix A phase diagram of the baseline mixture on the GPU: the
+    n x n composition grid below the excluded-volume line, one thread per
+    point (stability test, direct search, step-6(b) restarts, Newton polish)."""
+    import numpy as np
+    import torch
+
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd import phase
+
+    a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, 0.5)
+    NA, NB = phase.composition_grid(b, n)
+    phase.phase_points(1 / 3, a, b, NA[:64], NB[:64])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = phase.phase_points(1 / 3, a, b, NA, NB, max_iter=max_iter)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = r["status"].cpu().numpy()
+    pol = r["polished"].cpu().numpy()
+    it = r["iterations"].cpu().numpy()
+    return {"mixture": "theta_cr 0.4/0.4, rho_cr 1/1, nu 0.5, kT 1/3", "grid": n, "points": int(len(NA)),
+            "seconds": secs, "points_per_s": len(NA) / secs, "max_iter": max_iter,
+            "status_counts": {int(s): int((st == s).sum()) for s in np.unique(st)},
+            "polish_rejected": int((pol == 2).sum()), "mean_iterations_searched": float(it[it > 0].mean()),
+            "searched_at_cap": int((it >= max_iter).sum())}
+
+
+def verification_leg(n=16, steps=50000):
+    """The paper's verification workload: the two-phase points of an n x n
+    grid, minimiser on the GPU, one D1Q3 slab each at the computed phases,
+    `steps` steps in one batched launch (gamma_mu halved for runs that go
+    unphysical), bulk states against the binodal."""
+    import numpy as np
+
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd import phase
+    from paper_1805_07251_amd import verification as VV
+
+    out = {}
+    for name, nu in (("baseline", 0.5), ("identical", 1.0)):
+        a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, nu)
+        NA, NB = phase.composition_grid(b, n)
+        t0 = time.perf_counter()
+        r = VV.run(1 / 3, a, b, NA, NB, steps=steps)
+        secs = time.perf_counter() - t0
+        ok = r.status == 0
+        d = r.deviation[ok]
+        out[name] = {"runs": int(len(r.status)), "unphysical": int((~ok).sum()), "steps": steps, "seconds": secs,
+                     "deviation_median": float(np.nanmedian(d)), "deviation_p90": float(np.nanpercentile(d, 90)),
+                     "deviation_max": float(np.nanmax(d)), "frac_le_1e-4": float(np.mean(d <= 1e-4)),
+                     "frac_le_1e-3": float(np.mean(d <= 1e-3)),
+                     "gamma_halvings_histogram": np.bincount(r.halvings, minlength=5).tolist()}
+    return out
+
+
 def cpu_baseline(w, steps=8):
     """The CPU oracle on the same workload for a few steps (single thread)."""
     from oracle import oracle as O
@@ -459,6 +518,8 @@ def main():
         extra["d1q3_line_16M_f64"] = sweep_line(I.line_spinodal(args.seed, L=1 << 24), "f64", 2000, args.warmup)
         extra["batched_d1q3"] = batch_d1q3_leg(args.seed, 50000)
         extra["adjoint"] = adjoint_leg(args.seed)
+        extra["phase_diagram_256"] = phase_diagram_leg()
+        extra["verification"] = verification_leg()
     out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -19,6 +19,8 @@ long runs, Sec. VI, and the 2-D extension it announces in Sec. VII):
   batch_slabs      many quasi-1-D L x 4 lattices with a tanh liquid slab
                    (bulk densities from a caller-supplied coexistence solver)
   adjoint_case     256x256, spinodal_small parameters plus a smooth target
+  binary_mixture   a^{cc'}, b^c of the Sec. VI.A phase-diagram mixtures from
+                   their critical temperatures, critical densities and nu
 """
 from __future__ import annotations
 
@@ -213,3 +215,15 @@ def adjoint_case(seed: int = 0, n: int = 256):
     g /= np.abs(g).max()
     target = w.rho[0].mean() * (1.0 + 0.05 * g)
     return w, target
+
+
+def binary_mixture(theta_cr_a: float, theta_cr_b: float, rho_cr_a: float, rho_cr_b: float, nu: float):
+    """(a [2x2], b [2]) of a two-component mixture specified the way Sec. VI.A
+    specifies its phase diagrams: each component's critical temperature and
+    density fix b = 1/(3 rho_cr) and a = 9 theta_cr / (8 rho_cr) (Eqs. tetcr,
+    rhocr solved for a and b), and a^{AB} = nu sqrt(a^A a^B) (Eq. vdwConstantAB)."""
+    aa = 9.0 * theta_cr_a / (8.0 * rho_cr_a)
+    ab = 9.0 * theta_cr_b / (8.0 * rho_cr_b)
+    cross = nu * np.sqrt(aa * ab)
+    return np.array([[aa, cross], [cross, ab]]), np.array([1.0 / (3.0 * rho_cr_a), 1.0 / (3.0 * rho_cr_b)])
+

@@ -1,0 +1,62 @@
+"""GPU tests of the paper's verification workload: phase-diagram points from
+vdwlb_phase_points seed batched D1Q3 slabs, and the lattice's bulk states are
+measured against the binodal (Sec. VI.A)."""
+import numpy as np
+import pytest
+
+from oracle import thermo as T
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KT = 1 / 3
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_07251_amd import phase, verification
+
+    return phase, verification
+
+
+def test_identical_components_reach_the_binodal(mods):
+    """Two identical components (Fig. graphTwoIdenticalComponents): every
+    two-phase point of a 12 x 12 grid, run 200,000 steps from tanh slabs at
+    the minimiser's phases, ends within 1e-4 of the binodal (the paper's
+    figure of merit) and within 1e-4 of the pure fluid's Maxwell totals
+    (closed form) at the point's own composition."""
+    phase, V = mods
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 1.0)
+    gas, liq = T.maxwell_single(a[0, 0], b[0], KT)
+    NA, NB = phase.composition_grid(b, 12)
+    r = V.run(KT, a, b, NA, NB, steps=200000)
+    assert len(r.status) >= 10 and np.all(r.status == 0)
+    assert np.nanmax(r.deviation) <= 1e-4, r.deviation
+    for j in range(len(r.status)):
+        tot = np.sort(r.measured[j].sum(1))
+        np.testing.assert_allclose(tot, [gas, liq], atol=1e-4)
+        x = r.points[j, 0] / r.points[j].sum()
+        np.testing.assert_allclose(r.measured[j, :, 0] / r.measured[j].sum(1), [x, x], atol=1e-6)
+
+
+def test_baseline_mixture_runs(mods):
+    """The baseline Type III-H mixture (Fig. graphBaselineCase) on a 12 x 12
+    grid: the gamma_mu search leaves no unphysical run; after 50,000 steps
+    the median distance from the binodal is below 2e-3 (measured: ~1e-3 with
+    kappa = 0.4 on 256 sites; the paper reports mostly 1e-4 with its own,
+    unstated lattice sizes), and running on to 200,000 steps brings the
+    runs closer (material still diffusing between the phases, as the paper
+    notes)."""
+    phase, V = mods
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    NA, NB = phase.composition_grid(b, 12)
+    r1 = V.run(KT, a, b, NA, NB, steps=50000)
+    assert len(r1.status) >= 20 and np.all(r1.status == 0)
+    assert np.all(np.isfinite(r1.deviation))
+    assert np.median(r1.deviation) <= 2e-3
+    assert np.all(r1.deviation <= r1.end_deviation + 1e-5)  # chord vs curve: O(DELTA^2)
+    r2 = V.run(KT, a, b, NA, NB, steps=200000)
+    assert np.all(r2.status == 0)
+    assert np.median(r2.deviation) < np.median(r1.deviation)
