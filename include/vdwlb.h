@@ -194,8 +194,9 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* st
  * VDWLB_E_INVALID_ARG when kT >= kT_cr or a, b, kT are not positive. */
 vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, double* rho_liquid);
 
-/* Phase diagram of a two-component mixture (Appendix A), one GPU thread per
- * overall composition: point k holds NA[k] and NB[k] particles in a volume of 1.
+/* Phase diagram of a two-component mixture (Appendix A) over many overall
+ * compositions: point k holds NA[k] and NB[k] particles in a volume of 1.  The
+ * search gives each point a group of 16 lanes, one per trial move.
  *   - invalid (a density <= 0 or b . N >= 1): status -1, F = NaN, no phases;
  *   - Hessian of the bulk free energy positive definite (Sec. VI.A): stable,
  *     status 1, phases = {(NA, NB, 1)}, 0 iterations, no search;

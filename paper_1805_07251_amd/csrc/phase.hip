@@ -1,5 +1,7 @@
-// Phase diagram of a two-component van der Waals mixture (Appendix A), one
-// GPU thread per overall composition (A, B) in a volume of 1:
+// Phase diagram of a two-component van der Waals mixture (Appendix A) for
+// many overall compositions (A, B) in a volume of 1, each independent: the
+// search runs a 16-lane group per composition (one lane per trial move), the
+// classification and polish one thread per composition:
 //   1. stability: the Hessian of the bulk free-energy density at (A, B)
 //      (Sec. VI.A); a positive-definite point is one stable phase, no search;
 //   2. direct search over three phases: phases 1 and 2 hold (A1, B1, V1) and
@@ -29,6 +31,8 @@ namespace vdwlb {
 namespace {
 
 constexpr int PH_BLOCK = 64;             // one wave per workgroup: waves finish independently
+constexpr int PH_GROUP = 16;             // lanes per point in the search (12 trial moves)
+constexpr int PH_POINTS = PH_BLOCK / PH_GROUP;  // points per search workgroup
 constexpr int PH_RESTARTS = 2;           // restarts of step 6(b) per point
 constexpr int PH_MAX_ITER = 700000000;   // iterations of one search; (1 + PH_RESTARTS) of them fit an int32
 constexpr double MERGE_TOL = 1e-3;       // phases closer than this (max norm, relative to max(1, |rho|)) are one
@@ -315,48 +319,61 @@ __device__ __forceinline__ int count_unstable(const Mix& m, const Phase (&P)[3],
 constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_RESTART = 5, ST_STABLE_PENDING = 6;
 
 // The direct search from the amounts z = (A1, B1, V1, A2, B2, V2), phase 3
-// holding the rest of N.  Returns the final total free energy and adds the
+// holding the rest of N, run by a group of PH_GROUP lanes: lane l < 12 owns
+// the trial move of variable l / 2 by +step (l even) or -step (l odd), the
+// order in which a serial scan would try them.  Each iteration every lane
+// evaluates its trial (the moved phase and phase 3), the group takes the
+// lexicographic minimum of (free energy, lane) -- the first strict minimum,
+// as the serial scan finds it -- and every lane applies the winning move
+// with the winner's phase energies, so z, F and the step stay identical in
+// all lanes of the group.  Returns the final total free energy and adds the
 // iterations to iters.
-__device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double threshold, int max_iter, int& iters) {
+__device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double threshold, int max_iter, int& iters,
+                                int lane) {
     double e1 = phase_energy(m, z[0], z[1], z[2]);
     double e2 = phase_energy(m, z[3], z[4], z[5]);
     double e3 = phase_energy(m, N.a - z[0] - z[3], N.b - z[1] - z[4], 1.0 - z[2] - z[5]);
     double F = (e1 + e2) + e3;
     double step = 0.01;
+    const int k = lane >> 1;
+    const bool trial = lane < 12, minus = (lane & 1) != 0;
     for (int it = 0; it < max_iter; ++it) {
         ++iters;
-        double best = F, b1 = e1, b2 = e2, b3 = e3;
-        int bk = -1;
-        double bs = 0.0;
+        double Ft = INFINITY, t1 = e1, t2 = e2, t3 = e3;
+        if (trial) {
+            const double mv = minus ? -step : step;
+            double t[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
+            for (int j = 0; j < 6; ++j) t[j] = j == k ? z[j] + mv : z[j];
+            if (k < 3)
+                t1 = phase_energy(m, t[0], t[1], t[2]);
+            else
+                t2 = phase_energy(m, t[3], t[4], t[5]);
+            t3 = phase_energy(m, N.a - t[0] - t[3], N.b - t[1] - t[4], 1.0 - t[2] - t[5]);
+            Ft = (t1 + t2) + t3;
+        }
+        double best = Ft;
+        int bl = lane;
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const double mv = s == 0 ? step : -step;
-                double t[6] = {z[0], z[1], z[2], z[3], z[4], z[5]};
-                t[k] += mv;
-                const double t1 = k < 3 ? phase_energy(m, t[0], t[1], t[2]) : e1;
-                const double t2 = k < 3 ? e2 : phase_energy(m, t[3], t[4], t[5]);
-                const double t3 = phase_energy(m, N.a - t[0] - t[3], N.b - t[1] - t[4], 1.0 - t[2] - t[5]);
-                const double Ft = (t1 + t2) + t3;
-                if (Ft < best) {
-                    best = Ft;
-                    bk = k;
-                    bs = mv;
-                    b1 = t1;
-                    b2 = t2;
-                    b3 = t3;
-                }
+        for (int off = 1; off < PH_GROUP; off <<= 1) {
+            const double ob = __shfl_xor(best, off, PH_GROUP);
+            const int ol = __shfl_xor(bl, off, PH_GROUP);
+            if (ob < best || (ob == best && ol < bl)) {
+                best = ob;
+                bl = ol;
             }
         }
-        if (bk >= 0 && F - best > 0.0) {
+        if (best < F) {
+            const double w1 = __shfl(t1, bl, PH_GROUP), w2 = __shfl(t2, bl, PH_GROUP), w3 = __shfl(t3, bl, PH_GROUP);
+            const int bk = bl >> 1;
+            const double bs = (bl & 1) ? -step : step;
 #pragma unroll
             for (int j = 0; j < 6; ++j)
                 if (j == bk) z[j] += bs;
             F = best;
-            e1 = b1;
-            e2 = b2;
-            e3 = b3;
+            e1 = w1;
+            e2 = w2;
+            e3 = w3;
         } else {
             step *= 0.5;
             if (step < threshold) break;
@@ -365,17 +382,19 @@ __device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double thre
     return F;
 }
 
-// Steps 1 and 2: stability test and direct search.  First pass (restart = 0):
-// every point; writes the search's three phases (rho_A, rho_B, V) to raw,
-// its free energy to F and (status, iterations) to info[0..1].  Restart
-// passes: only points marked ST_RESTART, whose start amounts the classify
-// kernel left in raw[0..5]; iterations accumulate.
+// Steps 1 and 2: stability test and direct search, PH_GROUP lanes per point
+// (PH_POINTS points per workgroup; lane 0 of a group writes).  First pass
+// (restart = 0): every point; writes the search's three phases (rho_A,
+// rho_B, V) to raw, its free energy to F and (status, iterations) to
+// info[0..1].  Restart passes: only points marked ST_RESTART, whose start
+// amounts the classify kernel left in raw[0..5]; iterations accumulate.
 __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const double* __restrict__ NA,
                                                           const double* __restrict__ NB, double threshold,
                                                           int max_iter, int restart, double* __restrict__ raw,
                                                           double* __restrict__ Fout, int* __restrict__ info) {
-    const int i = blockIdx.x * PH_BLOCK + threadIdx.x;
-    if (i >= n) return;
+    const int lane = threadIdx.x & (PH_GROUP - 1);
+    const int i = blockIdx.x * PH_POINTS + (int)(threadIdx.x / PH_GROUP);
+    if (i >= n) return;  // whole groups leave together
     const Rho N{NA[i], NB[i]};
     double* w = raw + (int64_t)i * 9;
     double F = NAN;
@@ -386,7 +405,7 @@ __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const d
         iters = info[(int64_t)i * 4 + 1];
 #pragma unroll
         for (int k = 0; k < 6; ++k) z[k] = w[k];
-        F = direct_search(m, N, z, threshold, max_iter, iters);
+        F = direct_search(m, N, z, threshold, max_iter, iters, lane);
         status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
     } else if (admissible(m, N)) {
         F = free_density(m, N);
@@ -408,10 +427,11 @@ __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const d
             z[3] = N.a - z[0];
             z[4] = N.b - z[1];
             z[5] = V12;
-            F = direct_search(m, N, z, threshold, max_iter, iters);
+            F = direct_search(m, N, z, threshold, max_iter, iters, lane);
             status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
         }
     }
+    if (lane != 0) return;
     if (status == ST_SEARCHED || status == ST_FAILED) {
         // a phase of zero volume is reported with zero densities
         const double A3 = N.a - z[0] - z[3], B3 = N.b - z[1] - z[4], V3 = 1.0 - z[2] - z[5];
@@ -583,8 +603,9 @@ extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const dou
     const unsigned nb = (unsigned)((n + PH_BLOCK - 1) / PH_BLOCK);
     const hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
+    const unsigned nbs = (unsigned)((n + PH_POINTS - 1) / PH_POINTS);
     for (int pass = 0; pass <= PH_RESTARTS && e == hipSuccess; ++pass) {
-        hipLaunchKernelGGL(k_phase_search, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold,
+        hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold,
                            (int)max_iter, pass, raw, F, (int*)info);
         e = hipGetLastError();
         if (e != hipSuccess) break;
