@@ -42,6 +42,7 @@ struct Schedule {
     int tx, ty;
     bool nt;
     int occ;
+    int ry;  // rows of sites per thread
 };
 
 int schedule_count();

@@ -48,7 +48,18 @@ Coeffs<C, R> make_coeffs(const vdwlb_plan& p) {
     return k;
 }
 
-template <typename T, int C, int TX, int TY, bool NTS, int OCC>
+template <typename T, int C, int TX, int TY, bool NTS, int OCC, bool TAU1, bool MOM, int RY>
+void launch_tile(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom, const Geometry& g,
+                 const Coeffs<C, T>& k, int tiles) {
+    if constexpr (RY == 1)
+        hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, TAU1, MOM>), dim3(tiles), dim3(TX * TY), 0, s,
+                           (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+    else
+        hipLaunchKernelGGL((k_sweep_rows<T, C, TX, TY, NTS, OCC, TAU1, MOM, RY>), dim3(tiles), dim3(TX * TY / RY), 0,
+                           s, (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+}
+
+template <typename T, int C, int TX, int TY, bool NTS, int OCC, int RY>
 hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     const Geometry g = make_geometry(p, TX, TY);
     const Coeffs<C, T> k = make_coeffs<C, T>(p);
@@ -56,29 +67,25 @@ hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream
     if (mom) {  // the adjoint's recompute: FP64, C <= 2 only
         if constexpr (std::is_same<T, double>::value && C <= 2) {
             if (p.tau == 1.0)
-                hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, true, true>), dim3(tiles), dim3(TX * TY), 0, s,
-                                   (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+                launch_tile<T, C, TX, TY, NTS, OCC, true, true, RY>(p, fin, fout, s, mom, g, k, tiles);
             else
-                hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, false, true>), dim3(tiles), dim3(TX * TY), 0, s,
-                                   (const T*)fin, (T*)fout, g, k, p.d_flag, (T*)mom);
+                launch_tile<T, C, TX, TY, NTS, OCC, false, true, RY>(p, fin, fout, s, mom, g, k, tiles);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
     }
     if (p.tau == 1.0)
-        hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, true>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
-                           (T*)fout, g, k, p.d_flag, (T*)nullptr);
+        launch_tile<T, C, TX, TY, NTS, OCC, true, false, RY>(p, fin, fout, s, nullptr, g, k, tiles);
     else
-        hipLaunchKernelGGL((k_sweep<T, C, TX, TY, NTS, OCC, false>), dim3(tiles), dim3(TX * TY), 0, s, (const T*)fin,
-                           (T*)fout, g, k, p.d_flag, (T*)nullptr);
+        launch_tile<T, C, TX, TY, NTS, OCC, false, false, RY>(p, fin, fout, s, nullptr, g, k, tiles);
     return hipGetLastError();
 }
 
 template <typename T, int C>
 hipError_t run_sweep_sched(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     switch (p.sched) {
-#define VDWLB_SCHED_CASE(i, tx, ty, nt, occ) \
-    case i: return run_sweep<T, C, tx, ty, nt, occ>(p, fin, fout, s, mom);
+#define VDWLB_SCHED_CASE(i, tx, ty, nt, occ, ry) \
+    case i: return run_sweep<T, C, tx, ty, nt, occ, ry>(p, fin, fout, s, mom);
         VDWLB_SCHEDULES(VDWLB_SCHED_CASE)
 #undef VDWLB_SCHED_CASE
         default: return hipErrorInvalidValue;

@@ -584,6 +584,110 @@ k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C, T
     collide_store<T, C, NTSTORE, TAU1>(p, rho, jx, jy, gx, gy, lap, k, fout, g.plane, y * g.nx + x);
 }
 
+// The sweep with RY rows of sites per thread (RY > 1): the tile of k_sweep
+// with TX x TY / RY threads, thread row lt handling tile rows lt, lt + TY/RY,
+// ...  Fewer, fuller workgroups: a larger tile (a smaller density ring per
+// site) keeps several workgroups per CU.  With tau = 1 the collision does not
+// read the pulled populations, so a thread holds only each row's moments
+// across the barriers; otherwise it pulls a row's populations again in phase 3.
+template <typename T, int C, int TX, int TY, bool NTSTORE, int OCC, bool TAU1, bool MOM, int RY>
+__global__ void __launch_bounds__(TX * TY / RY) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+k_sweep_rows(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C, T> k, int* __restrict__ flag,
+        T* __restrict__ mom_out) {
+    static_assert(RY > 1 && TY % RY == 0, "RY must divide TY");
+    constexpr int TYT = TY / RY, NT = TX * TYT, EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2;
+    constexpr int RING = EX * EY - TX * TY;
+    __shared__ T s_rho[C][EY * EX];
+    __shared__ T s_phi[C][MY * MX];
+
+    int tx_, ty_;
+    xcd_tile(blockIdx.x, gridDim.x, g, tx_, ty_);
+    const int x0 = tx_ * TX, y0 = ty_ * TY;
+    const int lx = threadIdx.x % TX, lt = threadIdx.x / TX;
+    const int x = x0 + lx;
+    const int xs = wrapc(x, g.nx, g.wrap_general);
+
+    T p[C][Q];
+    T rho[RY][C], jx[RY][C], jy[RY][C];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int ly = lt + r * TYT, y = y0 + ly;
+        const int ys = wrapc(y, g.ny, g.wrap_general);
+        int o[Q];
+        pull_offsets(g, xs, ys, o);
+        pull<T, C>(fin, g, o, p);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rho[r][c] = density<T>(p[c]);
+            momentum<T>(p[c], jx[r][c], jy[r][c]);
+            if constexpr (TAU1 || C > 2) {  // fewer live registers (measured)
+                pin(jx[r][c]);
+                pin(jy[r][c]);
+            }
+            s_rho[c][(ly + 2) * EX + lx + 2] = rho[r][c];
+        }
+        if (MOM && x < g.nx && y < g.ny) {  // moments of the pulled state: rho [C][N], then j [C][2][N]
+            const int64_t n = (int64_t)g.nx * g.ny, site = (int64_t)y * g.nx + x;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                mom_out[c * n + site] = rho[r][c];
+                mom_out[(C + 2 * c) * n + site] = jx[r][c];
+                mom_out[(C + 2 * c + 1) * n + site] = jy[r][c];
+            }
+        }
+    }
+    for (int q = threadIdx.x; q < RING; q += NT) {
+        int ex, ey;
+        ring_coords<TX, TY>(q, ex, ey);
+        pull_density<T, C>(fin, g, wrapc(x0 - 2 + ex, g.nx, g.wrap_general), wrapc(y0 - 2 + ey, g.ny, g.wrap_general),
+                           &s_rho[0][ey * EX + ex], EY * EX);
+    }
+    __syncthreads();
+
+    bool bad = false;
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        T rr[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rr[c] = s_rho[c][(my + 1) * EX + mx + 1];
+            l[c] = lap9s<T, EX>(s_rho[c], mx + 1, my + 1);
+        }
+        bad |= !potential<T, C>(rr, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+    }
+    if (bad) atomicOr(flag, 1);
+    __syncthreads();
+
+    if (x >= g.nx) return;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int ly = lt + r * TYT, y = y0 + ly;
+        if (y >= g.ny) break;  // rows increase with r
+        if constexpr (!TAU1) {
+            int o[Q];
+            pull_offsets(g, xs, wrapc(y, g.ny, g.wrap_general), o);
+            pull<T, C>(fin, g, o, p);
+        }
+        T gx[C], gy[C], lap[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T px, py, rx, ry;
+            grad9s<T, MX>(s_phi[c], lx + 1, ly + 1, px, py);
+            grad9s<T, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
+            lap[c] = lap9s<T, EX>(s_rho[c], lx + 2, ly + 2);
+            gx[c] = -rho[r][c] * px;
+            gy[c] = -rho[r][c] * py;
+            if (k.force == 0) {
+                gx[c] += T(THETA) * rx;
+                gy[c] += T(THETA) * ry;
+            }
+        }
+        collide_store<T, C, NTSTORE, TAU1>(p, rho[r], jx[r], jy[r], gx, gy, lap, k, fout, g.plane, y * g.nx + x);
+    }
+}
+
 // f_i^c = f^0_i(rho^c, u^c) (Eq. feq).
 template <typename T, int C>
 __global__ void k_init(T* __restrict__ f, const T* __restrict__ rho, const T* __restrict__ mom, Geometry g) {

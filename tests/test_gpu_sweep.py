@@ -70,7 +70,7 @@ def test_spinodal_small_f32_1000_steps(gpu, orc):
     assert rel_err(np_(rho), rho_ref) <= 1e-4
 
 
-N_SCHED = 28
+N_SCHED = 40
 
 
 @pytest.mark.parametrize("sched", range(N_SCHED))
