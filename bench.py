@@ -430,11 +430,11 @@ def verification_leg(n=16, steps=50000):
     from paper_1805_07251_amd import verification as VV
 
     out = {}
-    for name, nu in (("baseline", 0.5), ("identical", 1.0)):
+    for name, nu, wi in (("baseline", 0.5, 0), ("identical", 1.0, 0), ("baseline_width_iterated", 0.5, 1)):
         a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, nu)
         NA, NB = phase.composition_grid(b, n)
         t0 = time.perf_counter()
-        r = VV.run(1 / 3, a, b, NA, NB, steps=steps)
+        r = VV.run(1 / 3, a, b, NA, NB, steps=steps, width_iterations=wi)
         secs = time.perf_counter() - t0
         ok = r.status == 0
         d = r.deviation[ok]
@@ -442,7 +442,8 @@ def verification_leg(n=16, steps=50000):
                      "deviation_median": float(np.nanmedian(d)), "deviation_p90": float(np.nanpercentile(d, 90)),
                      "deviation_max": float(np.nanmax(d)), "frac_le_1e-4": float(np.mean(d <= 1e-4)),
                      "frac_le_1e-3": float(np.mean(d <= 1e-3)),
-                     "gamma_halvings_histogram": np.bincount(r.halvings, minlength=5).tolist()}
+                     "gamma_halvings_histogram": np.bincount(r.halvings, minlength=5).tolist(),
+                     "width_iterations": wi, "width_median": float(np.median(r.widths))}
     return out
 
 

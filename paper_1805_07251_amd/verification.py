@@ -77,6 +77,16 @@ def slab_workloads(kT, a, b, phases, setup: SlabSetup = SlabSetup()):
     return ws
 
 
+def interface_width(rho, window):
+    """Equilibrium half-width of the two interfaces of a slab rho [C, L]: for
+    the component with the largest bulk contrast D, D / (2 max |d rho / dx|)
+    with the central difference (the w of a profile m + D/2 tanh(x / w))."""
+    inner, outer = bulk_states(rho, window)
+    c = int(np.argmax(np.abs(inner - outer)))
+    d = 0.5 * np.abs(np.roll(rho[c], -1) - np.roll(rho[c], 1))
+    return float(abs(inner[c] - outer[c]) / (2.0 * d.max()))
+
+
 def bulk_states(rho, window):
     """(slab centre, far edge) window means of rho [C, L]."""
     L = rho.shape[1]
@@ -97,6 +107,7 @@ class VerificationResult:
     steps: int
     gamma_mu: np.ndarray    # [m] gamma_mu of each instance's last run
     halvings: np.ndarray    # [m] times the stability search halved gamma_mu
+    widths: np.ndarray      # [m] interface width of each instance's last start
 
 
 def _matched(meas, ends):
@@ -108,7 +119,8 @@ def _matched(meas, ends):
     return min(d0, d1)
 
 
-def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=200000, gamma_halvings=4):
+def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=200000, gamma_halvings=4,
+        width_iterations=0):
     """Phase-diagram points (NA, NB) -> minimiser on the GPU -> one D1Q3 slab
     per polished two-phase point -> `steps` lattice Boltzmann steps in one
     batched launch -> bulk states against the binodal.
@@ -116,7 +128,12 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
     gamma_mu stability search (Sec. VI.A lowers gamma_mu for runs that go
     unstable): instances that end unphysical are run again from their
     initial profile with gamma_mu halved, up to `gamma_halvings` times, each
-    round one batched launch over the instances still failing."""
+    round one batched launch over the instances still failing.
+
+    Interface-width iteration (Sec. VI.A): `width_iterations` times, the
+    equilibrium width of each run's interfaces is measured and the run is
+    started again from tanh profiles at the minimiser's bulk values with
+    that width (and the gamma_mu it ended with)."""
     res = P.phase_points(kT, a, b, NA, NB, max_iter=max_iter)
     torch.cuda.synchronize()
     st = res["status"].cpu().numpy()
@@ -131,23 +148,35 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
     status = np.full(m, -1, dtype=np.int32)
     dens = [None] * m
     halvings = np.zeros(m, dtype=np.int32)
-    todo = np.arange(m)
-    for round_ in range(gamma_halvings + 1):
-        sub = [ws[j] for j in todo]
-        batch = Batch(sub, dtype="f64")
-        batch.init([w.rho for w in sub])
-        batch.run(steps)
-        st_b = batch.status()
-        rho_b = batch.densities()
-        for i, j in enumerate(todo):
-            status[j] = st_b[i]
-            dens[j] = rho_b[i].cpu().numpy()[:, 0]
-        todo = todo[st_b != 0]
-        if todo.size == 0 or round_ == gamma_halvings:
-            break
-        for j in todo:
-            ws[j].gamma_mu *= 0.5
-            halvings[j] += 1
+    widths = np.full(m, setup.width)
+    for it in range(width_iterations + 1):
+        if it > 0:
+            # restart from the minimiser's bulk values with the measured widths
+            for j in range(m):
+                if status[j] != 0:
+                    continue
+                widths[j] = interface_width(dens[j], setup.window)
+                p0, p1 = pairs[j]
+                dense, light = (p0, p1) if p0[0] + p0[1] >= p1[0] + p1[1] else (p1, p0)
+                n_in = int(np.clip(round(dense[2] * setup.L), 8, setup.L - 8))
+                ws[j].rho = two_phase_profile(setup.L, dense[:2], light[:2], n_in, widths[j])[:, None, :]
+        todo = np.arange(m)
+        for round_ in range(gamma_halvings + 1):
+            sub = [ws[j] for j in todo]
+            batch = Batch(sub, dtype="f64")
+            batch.init([w.rho for w in sub])
+            batch.run(steps)
+            st_b = batch.status()
+            rho_b = batch.densities()
+            for i, j in enumerate(todo):
+                status[j] = st_b[i]
+                dens[j] = rho_b[i].cpu().numpy()[:, 0]
+            todo = todo[st_b != 0]
+            if todo.size == 0 or round_ == gamma_halvings:
+                break
+            for j in todo:
+                ws[j].gamma_mu *= 0.5
+                halvings[j] += 1
     gamma = np.array([w.gamma_mu for w in ws])
     pred = np.empty((m, 2, 2))
     meas = np.empty((m, 2, 2))
@@ -194,4 +223,4 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
             d = max(d, abs(chord[0] * x[1] - chord[1] * x[0]) / nrm)
         dev[j] = d
     return VerificationResult(np.stack([np.asarray(NA, float)[keep], np.asarray(NB, float)[keep]], 1), pred, meas,
-                              bino, shift, dev, end_dev, status, steps, gamma, halvings)
+                              bino, shift, dev, end_dev, status, steps, gamma, halvings, widths)
