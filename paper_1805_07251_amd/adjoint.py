@@ -56,6 +56,7 @@ class Spec:
     gamma_mu: float = 1.0
     lam: np.ndarray | None = None
     force: int = V.FORCE_LOG
+    schedule: int | None = None  # sweep schedule of the forward and recompute (default: the plan's)
 
 
 class VdwLBFunction(torch.autograd.Function):
@@ -64,6 +65,8 @@ class VdwLBFunction(torch.autograd.Function):
         th = theta.detach().cpu().numpy().astype(np.float64)
         kT, a, b, kappa = params_from_theta(th, spec.C, spec.k_hat)
         plan = Plan(spec.nx, spec.ny, kT, a, b, kappa, spec.tau, spec.gamma_mu, spec.lam, "f64", spec.force)
+        if spec.schedule is not None:
+            V.check(V.lib().vdwlb_set_schedule(plan.handle, int(spec.schedule)), "vdwlb_set_schedule")
         dev = rho0.device
         n = plan.state_elems
         bufs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]

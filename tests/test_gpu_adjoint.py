@@ -247,3 +247,30 @@ def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
     for loss, grad in graphed:
         assert loss == eager[0]
         assert np.array_equal(grad, eager[1])
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_row_schedules_equal_default(gpu, tau):
+    """The recompute inside the backward pass runs the plan's sweep schedule
+    in its moment-writing form; the schedules with several rows of sites per
+    thread (tau = 1 keeps only the rows' moments, tau != 1 pulls again) must
+    give the default schedule's loss and gradient bit for bit."""
+    adjoint, _, _ = gpu
+    P = mixture(2, tau=tau)
+    k_hat = P["kappa"] / 0.1
+    nx, ny, nsteps = 70, 37, 30
+    rng = np.random.default_rng(11)
+    rho0 = 2.625 * (1 + 0.01 * rng.uniform(-1, 1, (2, ny, nx)))
+    tg = torch.as_tensor(rho0[0].mean() * (1 + 0.05 * np.cos(2 * np.pi * np.arange(nx) / nx))[None, :].repeat(ny, 0),
+                         device="cuda")
+    theta = adjoint.theta_from_params(P["kT"], P["a"], P["b"], 0.1)
+    loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
+    r0 = torch.as_tensor(rho0, device="cuda")
+    out = []
+    for sched in (None, 14, 15, 36):
+        spec = adjoint.Spec(nx, ny, 2, k_hat, nsteps, ckpt=10, tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"],
+                            schedule=sched)
+        out.append(adjoint.run_and_grad(theta, r0, spec, loss_fn))
+    for loss, grad in out[1:]:
+        assert loss == out[0][0]
+        assert np.array_equal(grad, out[0][1])

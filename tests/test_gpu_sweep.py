@@ -86,16 +86,34 @@ def test_populations_one_step_every_schedule(gpu, orc, sched):
     np.testing.assert_allclose(f, ref.f, rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("sched", [15, 19, 25])
+@pytest.mark.parametrize("sched", [21, 25, 34])
 def test_band_mapping_against_oracle(gpu, orc, sched):
-    """Vertical XCD bands (schedules 14..27) on a lattice whose tile columns
-    divide by 8."""
+    """Vertical XCD bands (schedules 20..39: 64x8, 32x16 and two rows per
+    thread on 64x16) on a lattice whose tile columns divide by 8."""
     w = I.spinodal_small(1, n=64)
     w.nx, w.ny = 512, 37
     w.rho = np.random.default_rng(13).uniform(2.5, 2.75, (2, 37, 512))
     ref, _ = oracle_run(orc, w, 3)
     lat = gpu_run(gpu, w, 3, sched=sched)
     np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-14)
+
+
+def test_every_schedule_tau_and_three_components(gpu, orc):
+    """Every schedule with tau != 1 (the collision reads the pulled
+    populations: kernels with several rows per thread pull them again) and
+    three components (friction by elimination) against the oracle, 3 steps
+    on a ragged lattice."""
+    w = I.mixture4(5, n=80, dtype="f64", C=3)
+    w.nx, w.ny = 77, 45
+    w.tau = 0.8
+    rng = np.random.default_rng(21)
+    w.rho = w.rho[:, :45, :77] * (1 + 0.01 * rng.uniform(-1, 1, (3, 45, 77)))
+    ref, _ = oracle_run(orc, w, 3)
+    scale = np.abs(ref.f).max()
+    for s in range(N_SCHED):
+        lat = gpu_run(gpu, w, 3, sched=s)
+        err = np.abs(np_(lat.state_sites()) - ref.f).max()
+        assert err <= 1e-13 * scale, (s, err)
 
 
 def test_schedules_bitwise_identical(gpu):
