@@ -430,6 +430,17 @@ def verification_leg(n=16, steps=50000):
     from paper_1805_07251_amd import verification as VV
 
     out = {}
+    a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, 0.5)
+    NA, NB = phase.composition_grid(b, 64)
+    t0 = time.perf_counter()
+    r = VV.run_three_phase(1 / 3, a, b, NA, NB, steps=steps, setup=VV.SlabSetup(kappa=0.1))
+    secs = time.perf_counter() - t0
+    ok = r.status == 0
+    out["baseline_three_phase"] = {"grid": 64, "kappa": 0.1, "runs": int(len(r.status)),
+                                   "unphysical": int((~ok).sum()), "steps": steps, "seconds": secs,
+                                   "deviation_median": float(np.median(r.deviation[ok])),
+                                   "deviation_p90": float(np.percentile(r.deviation[ok], 90)),
+                                   "deviation_max": float(r.deviation[ok].max())}
     for name, nu, wi in (("baseline", 0.5, 0), ("identical", 1.0, 0), ("baseline_width_iterated", 0.5, 1)):
         a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, nu)
         NA, NB = phase.composition_grid(b, n)

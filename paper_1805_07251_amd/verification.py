@@ -224,3 +224,107 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
         dev[j] = d
     return VerificationResult(np.stack([np.asarray(NA, float)[keep], np.asarray(NB, float)[keep]], 1), pred, meas,
                               bino, shift, dev, end_dev, status, steps, gamma, halvings, widths)
+
+
+def three_phase_profile(L, gas, lq_a, lq_b, na, nb, width):
+    """[2, L] densities: gas | A-rich liquid | gas | B-rich liquid | gas, the
+    liquids on na and nb sites, the gas split into two domains of equal size
+    (the first and last pieces are one domain across the periodic boundary),
+    tanh edges of the given width."""
+    ng = L - na - nb
+    e0 = ng // 4
+    e1 = e0 + na
+    e2 = e1 + ng // 2
+    e3 = e2 + nb
+    x = np.arange(L, dtype=np.float64) + 0.5
+    box = lambda lo, hi: 0.5 * (np.tanh((x - lo) / width) - np.tanh((x - hi) / width))
+    g, la, lb = (np.asarray(v, float) for v in (gas, lq_a, lq_b))
+    prof = g[:, None] + (la - g)[:, None] * box(e0, e1)[None, :] + (lb - g)[:, None] * box(e2, e3)[None, :]
+    centres = [((e3 + L + e0) // 2) % L, (e0 + e1) // 2, (e1 + e2) // 2, (e2 + e3) // 2]
+    return prof, centres
+
+
+@dataclass
+class ThreePhaseResult:
+    points: np.ndarray      # [m, 2] overall compositions run
+    predicted: np.ndarray   # [m, 3, 2] gas, A-rich, B-rich phases of the minimiser
+    measured: np.ndarray    # [m, 4, 2] bulk states at the centres of gas, A-rich, gas, B-rich
+    deviation: np.ndarray   # [m] max |measured - predicted| over the four domains
+    status: np.ndarray      # [m] batch status
+    steps: int
+    gamma_mu: np.ndarray
+    halvings: np.ndarray
+
+
+def run_three_phase(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=200000,
+                    gamma_halvings=4, min_domain=12):
+    """The verification of the three-phase regions: every polished
+    three-phase point of (NA, NB) is run as a D1Q3 line with tanh domains of
+    the minimiser's three phases (gas | A-rich | gas | B-rich, the gas being
+    the phase of lowest total density), sized by the lever rule; points whose
+    smallest domain would have fewer than `min_domain` sites are skipped.
+    The three-phase state of a binary mixture is unique at fixed temperature
+    (Gibbs phase rule), so every run should end at the same densities: the
+    deviation is the largest distance of a domain's bulk state from them.
+    gamma_mu is halved for runs that go unphysical, as in `run`."""
+    res = P.phase_points(kT, a, b, NA, NB, max_iter=max_iter)
+    torch.cuda.synchronize()
+    st = res["status"].cpu().numpy()
+    pol = res["polished"].cpu().numpy()
+    ph = res["phases"].cpu().numpy()
+    kap = I.kappa_matrix(np.asarray(a, float), setup.kappa)
+    ws, preds, cents, pts = [], [], [], []
+    for k in np.flatnonzero((st == 3) & (pol == 1)):
+        phases = ph[k]
+        g = int(np.argmin(phases[:, 0] + phases[:, 1]))
+        rest = [q for q in range(3) if q != g]
+        ia = max(rest, key=lambda q: phases[q, 0] - phases[q, 1])
+        ib = min(rest, key=lambda q: phases[q, 0] - phases[q, 1])
+        na, nb = int(round(phases[ia, 2] * setup.L)), int(round(phases[ib, 2] * setup.L))
+        ng = setup.L - na - nb
+        if min(na, nb, ng // 2) < min_domain:
+            continue
+        prof, centres = three_phase_profile(setup.L, phases[g, :2], phases[ia, :2], phases[ib, :2], na, nb,
+                                            setup.width)
+        rho_l = max(phases[ia, :2].sum(), phases[ib, :2].sum())
+        gam = setup.gamma_scale * (1.0 - CS2) / (4.0 * setup.kappa * rho_l)
+        ws.append(I.Workload(setup.L, 1, kT, np.asarray(a, float), np.asarray(b, float), kap, prof[:, None, :],
+                             tau=setup.tau, gamma_mu=gam, dim=1))
+        preds.append(np.stack([phases[g, :2], phases[ia, :2], phases[ib, :2]]))
+        cents.append(centres)
+        pts.append((NA[k], NB[k]))
+    m = len(ws)
+    if m == 0:
+        raise ValueError("no three-phase point with domains of at least min_domain sites")
+    status = np.full(m, -1, dtype=np.int32)
+    dens = [None] * m
+    halvings = np.zeros(m, dtype=np.int32)
+    todo = np.arange(m)
+    for round_ in range(gamma_halvings + 1):
+        sub = [ws[j] for j in todo]
+        batch = Batch(sub, dtype="f64")
+        batch.init([w.rho for w in sub])
+        batch.run(steps)
+        st_b = batch.status()
+        rho_b = batch.densities()
+        for i, j in enumerate(todo):
+            status[j] = st_b[i]
+            dens[j] = rho_b[i].cpu().numpy()[:, 0]
+        todo = todo[st_b != 0]
+        if todo.size == 0 or round_ == gamma_halvings:
+            break
+        for j in todo:
+            ws[j].gamma_mu *= 0.5
+            halvings[j] += 1
+    pred = np.array(preds)
+    meas = np.empty((m, 4, 2))
+    dev = np.empty(m)
+    win = np.arange(-setup.window, setup.window + 1)
+    for j in range(m):
+        L = dens[j].shape[1]
+        for q, c in enumerate(cents[j]):
+            meas[j, q] = dens[j][:, (c + win) % L].mean(1)
+        want = np.stack([pred[j, 0], pred[j, 1], pred[j, 0], pred[j, 2]])
+        dev[j] = np.abs(meas[j] - want).max()
+    return ThreePhaseResult(np.array(pts), pred, meas, dev, status, steps, np.array([w.gamma_mu for w in ws]),
+                            halvings)
