@@ -47,6 +47,8 @@ def parse():
                     help="profiling run: the headline sweep for --steps steps and the 1 GiB copy kernel only")
     ap.add_argument("--schedule", type=int, default=-1,
                     help="with --profile: use this sweep schedule instead of autotuning")
+    ap.add_argument("--phase", action="store_true",
+                    help="profiling run: the 256 x 256 Appendix A phase-diagram leg only")
     return ap.parse_args()
 
 
@@ -487,6 +489,9 @@ def main():
     from paper_1805_07251_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.phase:
+        print(json.dumps({"profile": True, "phase_diagram_256": phase_diagram_leg()}))
+        return
     w = I.spinodal_large(args.seed)
     head = sweep_line(w, "f64", args.steps, args.warmup, args.schedule if args.profile else -1)
     if args.profile:

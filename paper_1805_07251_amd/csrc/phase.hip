@@ -298,14 +298,77 @@ __device__ bool polish(const Mix& m, Rho N, double F_search, Phase (&P)[3], int 
     return true;
 }
 
+__device__ __forceinline__ void cmpswap(Phase& p, Phase& q) {
+    if ((q.a - q.b) < (p.a - p.b)) {
+        const Phase t = p;
+        p = q;
+        q = t;
+    }
+}
+
+// Sort the first n <= 3 phases by rho_A - rho_B (the insertion sort's order,
+// as a fixed compare-and-swap network so the phases stay in registers).
 __device__ __forceinline__ void sort_phases(Phase (&P)[3], int n) {
-    // insertion sort by rho_A - rho_B (n <= 3)
-    for (int i = 1; i < n; ++i)
-        for (int j = i; j > 0 && (P[j].a - P[j].b) < (P[j - 1].a - P[j - 1].b); --j) {
-            const Phase t = P[j];
-            P[j] = P[j - 1];
-            P[j - 1] = t;
+    if (n >= 2) cmpswap(P[0], P[1]);
+    if (n >= 3) {
+        cmpswap(P[1], P[2]);
+        cmpswap(P[0], P[1]);
+    }
+}
+
+// Step 6 classification of the search's phases R: merged greedily in their
+// order when their densities agree within MERGE_TOL (particles and volumes
+// add), merged phases below VOLUME_MIN dropped, the rest sorted.  Returns
+// their number; every array index is a compile-time constant.
+__device__ __forceinline__ int distinct_phases(const Phase (&R)[3], Phase (&P)[3]) {
+    double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gV[3] = {0.0, 0.0, 0.0};
+    int ng = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (!(R[q].v > 0.0)) continue;
+        int hit = -1;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            if (g < ng && hit < 0) {
+                const double ra = gA[g] / gV[g], rb = gB[g] / gV[g];
+                const double scale = fmax(1.0, fmax(fabs(ra), fabs(rb)));
+                if (fmax(fabs(R[q].a - ra), fabs(R[q].b - rb)) <= MERGE_TOL * scale) hit = g;
+            }
         }
+        if (hit < 0) hit = ng++;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            if (g == hit) {
+                gA[g] += R[q].a * R[q].v;
+                gB[g] += R[q].b * R[q].v;
+                gV[g] += R[q].v;
+            }
+        }
+    }
+    int np = 0;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        if (g < ng && gV[g] >= VOLUME_MIN) {
+            const Phase ph{gA[g] / gV[g], gB[g] / gV[g], gV[g]};
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                if (s == np) P[s] = ph;
+            ++np;
+        }
+    }
+    sort_phases(P, np);
+    return np;
+}
+
+// The search's three phases (rho_A, rho_B, V) from the amounts z, phase 3
+// holding the rest of N; a phase of zero volume has zero densities.
+__device__ __forceinline__ void raw_phases(Rho N, const double (&z)[6], Phase (&R)[3]) {
+    const double q[9] = {z[0], z[1], z[2], z[3], z[4], z[5], N.a - z[0] - z[3], N.b - z[1] - z[4], 1.0 - z[2] - z[5]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double V = q[3 * k + 2];
+        R[k] = Phase{V > 0.0 ? q[3 * k + 0] / V : 0.0, V > 0.0 ? q[3 * k + 1] / V : 0.0, V};
+    }
 }
 
 __device__ __forceinline__ int count_unstable(const Mix& m, const Phase (&P)[3], int n) {
@@ -316,7 +379,7 @@ __device__ __forceinline__ int count_unstable(const Mix& m, const Phase (&P)[3],
 
 // Status codes between the kernels: the public ones (-1 invalid, 0 failed,
 // 1..3 phases) are final; the others mark work still to do.
-constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_RESTART = 5, ST_STABLE_PENDING = 6;
+constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_STABLE_PENDING = 6;
 
 // The direct search from the amounts z = (A1, B1, V1, A2, B2, V2), phase 3
 // holding the rest of N, run by a group of PH_GROUP lanes: lane l < 12 owns
@@ -382,32 +445,57 @@ __device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double thre
     return F;
 }
 
-// Steps 1 and 2: stability test and direct search, PH_GROUP lanes per point
-// (PH_POINTS points per workgroup; lane 0 of a group writes).  First pass
-// (restart = 0): every point; writes the search's three phases (rho_A,
-// rho_B, V) to raw, its free energy to F and (status, iterations) to
-// info[0..1].  Restart passes: only points marked ST_RESTART, whose start
-// amounts the classify kernel left in raw[0..5]; iterations accumulate.
+// Step 6(b): if the distinct phases of the search's end state z include an
+// unstable one, replace z by the start of a new search (the largest unstable
+// phase split along its unstable direction into phases 1 and 2, phase 3 then
+// holding the other phases packed together) and return true.  Kept out of
+// line so that the search loop's register allocation does not carry it.
+__device__ __noinline__ bool restart_start(const Mix& m, Rho N, double (&z)[6]) {
+    Phase R[3], P[3];
+    raw_phases(N, z, R);
+    const int np = distinct_phases(R, P);
+    int u = -1;
+    Phase pu{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (q < np && !stable(m, Rho{P[q].a, P[q].b}) && (u < 0 || P[q].v > pu.v)) {
+            u = q;
+            pu = P[q];
+        }
+    }
+    if (u < 0) return false;
+    const double Au = pu.a * pu.v, Bu = pu.b * pu.v, Vu = pu.v;
+    const Rho du = unstable_direction(hessian(m, Rho{pu.a, pu.b}));
+    const double eps = 0.05 * fmin(Au, Bu);
+    z[0] = 0.5 * Au + 0.5 * eps * du.a;
+    z[1] = 0.5 * Bu + 0.5 * eps * du.b;
+    z[2] = 0.5 * Vu;
+    z[3] = Au - z[0];
+    z[4] = Bu - z[1];
+    z[5] = 0.5 * Vu;
+    return true;
+}
+
+// Steps 1 and 2 with the restarts of step 6(b): stability test, direct
+// search, and, while the search ends with an unstable distinct phase (at most
+// PH_RESTARTS times), a new search with the largest unstable phase split
+// along its unstable direction into phases 1 and 2 and phase 3 holding the
+// other phases packed together.  PH_GROUP lanes per point (PH_POINTS points
+// per workgroup; every lane of a group takes the same decisions, lane 0
+// writes).  Writes the last search's three phases (rho_A, rho_B, V) to raw,
+// its free energy to F and (status, iterations of all searches) to info[0..1].
 __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const double* __restrict__ NA,
                                                           const double* __restrict__ NB, double threshold,
-                                                          int max_iter, int restart, double* __restrict__ raw,
+                                                          int max_iter, double* __restrict__ raw,
                                                           double* __restrict__ Fout, int* __restrict__ info) {
     const int lane = threadIdx.x & (PH_GROUP - 1);
     const int i = blockIdx.x * PH_POINTS + (int)(threadIdx.x / PH_GROUP);
     if (i >= n) return;  // whole groups leave together
     const Rho N{NA[i], NB[i]};
-    double* w = raw + (int64_t)i * 9;
     double F = NAN;
     int status = ST_INVALID, iters = 0;
     double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (restart) {
-        if (info[(int64_t)i * 4 + 0] != ST_RESTART) return;
-        iters = info[(int64_t)i * 4 + 1];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) z[k] = w[k];
-        F = direct_search(m, N, z, threshold, max_iter, iters, lane);
-        status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
-    } else if (admissible(m, N)) {
+    if (admissible(m, N)) {
         F = free_density(m, N);
         const Sym2 h = hessian(m, N);
         if (h.xx > 0.0 && h.xx * h.yy - h.xy * h.xy > 0.0) {
@@ -427,21 +515,23 @@ __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const d
             z[3] = N.a - z[0];
             z[4] = N.b - z[1];
             z[5] = V12;
-            F = direct_search(m, N, z, threshold, max_iter, iters, lane);
+            for (int restart = 0;; ++restart) {
+                F = direct_search(m, N, z, threshold, max_iter, iters, lane);
+                if (!isfinite(F) || restart == PH_RESTARTS || !restart_start(m, N, z)) break;
+            }
             status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
         }
     }
     if (lane != 0) return;
+    double* w = raw + (int64_t)i * 9;
     if (status == ST_SEARCHED || status == ST_FAILED) {
-        // a phase of zero volume is reported with zero densities
-        const double A3 = N.a - z[0] - z[3], B3 = N.b - z[1] - z[4], V3 = 1.0 - z[2] - z[5];
-        const double q[9] = {z[0], z[1], z[2], z[3], z[4], z[5], A3, B3, V3};
+        Phase R[3];
+        raw_phases(N, z, R);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double V = q[3 * k + 2];
-            w[3 * k + 0] = V > 0.0 ? q[3 * k + 0] / V : 0.0;
-            w[3 * k + 1] = V > 0.0 ? q[3 * k + 1] / V : 0.0;
-            w[3 * k + 2] = V;
+            w[3 * k + 0] = R[k].a;
+            w[3 * k + 1] = R[k].b;
+            w[3 * k + 2] = R[k].v;
         }
     } else {
 #pragma unroll
@@ -452,17 +542,12 @@ __global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const d
     info[(int64_t)i * 4 + 1] = iters;
 }
 
-// Steps 3 and 4: classification and polish of the searched points, with the
-// restart of step 6(b): while restarts_left > 0, a point whose distinct
-// phases include an unstable one is sent back to the search (ST_RESTART)
-// with that phase (the largest unstable one) split along its unstable
-// direction into phases 1 and 2, and phase 3 holding the others packed
-// together; the start amounts go to raw[0..5].  Otherwise writes phases and
-// completes info (final status, -, n_unstable, polished).  Points finished
-// in an earlier pass are left alone.
+// Steps 3 and 4: classification and polish of the searched points, one
+// thread per point.  Writes phases and completes info (final status, -,
+// n_unstable, polished).
 __global__ void __launch_bounds__(PH_BLOCK) k_phase_classify(Mix m, int n, const double* __restrict__ NA,
-                                                            const double* __restrict__ NB, int restarts_left,
-                                                            double* __restrict__ raw,
+                                                            const double* __restrict__ NB,
+                                                            const double* __restrict__ raw,
                                                             const double* __restrict__ Fs,
                                                             double* __restrict__ phases, int* __restrict__ info) {
     const int i = blockIdx.x * PH_BLOCK + threadIdx.x;
@@ -470,52 +555,15 @@ __global__ void __launch_bounds__(PH_BLOCK) k_phase_classify(Mix m, int n, const
     const Rho N{NA[i], NB[i]};
     Phase P[3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     int status = info[(int64_t)i * 4 + 0], unstable_n = 0, polished = 0;
-    if (status >= 1 && status <= 3) return;
     if (status == ST_STABLE_PENDING) {
         status = 1;
         P[0] = Phase{N.a, N.b, 1.0};
     } else if (status == ST_SEARCHED) {
-        double* w = raw + (int64_t)i * 9;
+        const double* w = raw + (int64_t)i * 9;
         const Phase R[3] = {{w[0], w[1], w[2]}, {w[3], w[4], w[5]}, {w[6], w[7], w[8]}};
-        // merge greedily in search order (particles and volumes add)
-        double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gV[3] = {0.0, 0.0, 0.0};
-        int ng = 0;
-        for (int q = 0; q < 3; ++q) {
-            if (!(R[q].v > 0.0)) continue;
-            int hit = -1;
-            for (int g = 0; g < ng && hit < 0; ++g) {
-                const double ra = gA[g] / gV[g], rb = gB[g] / gV[g];
-                const double scale = fmax(1.0, fmax(fabs(ra), fabs(rb)));
-                if (fmax(fabs(R[q].a - ra), fabs(R[q].b - rb)) <= MERGE_TOL * scale) hit = g;
-            }
-            if (hit < 0) hit = ng++;
-            gA[hit] += R[q].a * R[q].v;
-            gB[hit] += R[q].b * R[q].v;
-            gV[hit] += R[q].v;
-        }
-        int np = 0;
-        for (int g = 0; g < ng; ++g)
-            if (gV[g] >= VOLUME_MIN) P[np++] = Phase{gA[g] / gV[g], gB[g] / gV[g], gV[g]};
-        sort_phases(P, np);
+        const int np = distinct_phases(R, P);
         status = np;
         unstable_n = count_unstable(m, P, np);
-        if (restarts_left > 0 && unstable_n > 0) {
-            int u = -1;
-            for (int q = 0; q < np; ++q)
-                if (!stable(m, Rho{P[q].a, P[q].b}) && (u < 0 || P[q].v > P[u].v)) u = q;
-            const double Au = P[u].a * P[u].v, Bu = P[u].b * P[u].v, Vu = P[u].v;
-            const Rho d = unstable_direction(hessian(m, Rho{P[u].a, P[u].b}));
-            const double eps = 0.05 * fmin(Au, Bu);
-            const double A1 = 0.5 * Au + 0.5 * eps * d.a, B1 = 0.5 * Bu + 0.5 * eps * d.b;
-            w[0] = A1;
-            w[1] = B1;
-            w[2] = 0.5 * Vu;
-            w[3] = Au - A1;
-            w[4] = Bu - B1;
-            w[5] = 0.5 * Vu;
-            info[(int64_t)i * 4 + 0] = ST_RESTART;
-            return;
-        }
         if (np == 2 || np == 3) {
             if (polish(m, N, Fs[i], P, np)) {
                 polished = 1;
@@ -602,15 +650,13 @@ extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const dou
     const Mix m{kT, a[0], a[1], a[3], b[0], b[1]};
     const unsigned nb = (unsigned)((n + PH_BLOCK - 1) / PH_BLOCK);
     const hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
     const unsigned nbs = (unsigned)((n + PH_POINTS - 1) / PH_POINTS);
-    for (int pass = 0; pass <= PH_RESTARTS && e == hipSuccess; ++pass) {
-        hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold,
-                           (int)max_iter, pass, raw, F, (int*)info);
-        e = hipGetLastError();
-        if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_phase_classify, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, PH_RESTARTS - pass,
-                           raw, (const double*)F, phases, (int*)info);
+    hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold, (int)max_iter,
+                       raw, F, (int*)info);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_phase_classify, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, (const double*)raw,
+                           (const double*)F, phases, (int*)info);
         e = hipGetLastError();
     }
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, "phase-point kernels");
