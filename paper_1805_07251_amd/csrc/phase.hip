@@ -408,10 +408,12 @@ __device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double thre
             double t[6];
 #pragma unroll
             for (int j = 0; j < 6; ++j) t[j] = j == k ? z[j] + mv : z[j];
-            if (k < 3)
-                t1 = phase_energy(m, t[0], t[1], t[2]);
-            else
-                t2 = phase_energy(m, t[3], t[4], t[5]);
+            // the moved phase (1 or 2) selected first, so that all trial lanes
+            // run one phase-energy evaluation instead of both branches
+            const bool first = k < 3;
+            const double em = phase_energy(m, first ? t[0] : t[3], first ? t[1] : t[4], first ? t[2] : t[5]);
+            t1 = first ? em : e1;
+            t2 = first ? e2 : em;
             t3 = phase_energy(m, N.a - t[0] - t[3], N.b - t[1] - t[4], 1.0 - t[2] - t[5]);
             Ft = (t1 + t2) + t3;
         }
@@ -484,7 +486,8 @@ __device__ __noinline__ bool restart_start(const Mix& m, Rho N, double (&z)[6]) 
 // per workgroup; every lane of a group takes the same decisions, lane 0
 // writes).  Writes the last search's three phases (rho_A, rho_B, V) to raw,
 // its free energy to F and (status, iterations of all searches) to info[0..1].
-__global__ void __launch_bounds__(PH_BLOCK) k_phase_search(Mix m, int n, const double* __restrict__ NA,
+__global__ void __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_phase_search(Mix m, int n, const double* __restrict__ NA,
                                                           const double* __restrict__ NB, double threshold,
                                                           int max_iter, double* __restrict__ raw,
                                                           double* __restrict__ Fout, int* __restrict__ info) {
