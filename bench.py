@@ -356,36 +356,46 @@ def adjoint_leg(seed):
     spec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
     rho0 = torch.as_tensor(w.rho, device="cuda")
     tg = torch.as_tensor(tgt, device="cuda")
-    # warm-up (plans, graphs, allocator)
+    # warm-up (allocator, code objects); each call below builds its own plan and
+    # captures its graphs, as a caller of the autograd function does
     A.run_and_grad(theta, rho0, spec, lambda r: ((r[0] - tg) ** 2).sum())
     torch.cuda.synchronize()
-    t = torch.as_tensor(theta).clone().requires_grad_(True)
-    t0 = time.perf_counter()
-    rho = A.VdwLBFunction.apply(t, rho0, spec)
-    loss = ((rho[0] - tg) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    # the plain forward for the same 2000 steps
+    fwd, bwd = [], []
+    for _ in range(3):
+        t = torch.as_tensor(theta).clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        rho = A.VdwLBFunction.apply(t, rho0, spec)
+        loss = ((rho[0] - tg) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd.append(t1 - t0)
+        bwd.append(t2 - t1)
+    # the plain forward for the same 2000 steps (its step graph captured beforehand)
     lat = Lattice.from_workload(w)
     lat.init(w.rho)
-    lat.run(10)
+    lat.run(64)
     torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    lat.init(w.rho)
-    lat.run(2000)
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
+    plain = []
+    for _ in range(3):
+        lat.init(w.rho)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        lat.run(2000)
+        torch.cuda.synchronize()
+        plain.append(time.perf_counter() - t3)
+    f, b, pf = min(fwd), min(bwd), min(plain)
     sites = w.nx * w.ny
     return {
         "workload": "256x256 D2Q9, C=2, FP64, 2000 steps, checkpoints every 100",
-        "forward_ms": (t1 - t0) * 1e3,
-        "backward_ms": (t2 - t1) * 1e3,
-        "plain_forward_ms": (t4 - t3) * 1e3,
-        "fwd_plus_bwd_over_plain_forward": ((t2 - t0) / (t4 - t3)),
-        "adjoint_mlups": sites * 2000 / (t2 - t1) / 1e6,
+        "timing": "best of 3 of each",
+        "forward_ms": f * 1e3,
+        "backward_ms": b * 1e3,
+        "plain_forward_ms": pf * 1e3,
+        "fwd_plus_bwd_over_plain_forward": (f + b) / pf,
+        "adjoint_mlups": sites * 2000 / b / 1e6,
         "loss": float(loss.detach().cpu()),
         "grad": [float(v) for v in t.grad.cpu().numpy()],
         "theta_names": ["kT", "a11", "a12", "a22", "b1", "b2", "kappa"],

@@ -23,6 +23,8 @@
 #include <cstdio>
 #include <vector>
 
+#include <cstdlib>
+
 #include "../../include/vdwlb.h"
 #include "launch.hpp"
 
@@ -221,6 +223,189 @@ __device__ __forceinline__ double lapg(const double* a, const Geometry& g, int x
     return (4.0 * axis + diag - 20.0 * a[r0 + x]) * (1.0 / 6.0);
 }
 
+// Kernel CA: the un-stream of step t (kernel C) fused with kernel A of step
+// t - 1.  The cotangent kernel C would scatter from site x to x - v_i is
+// gathered here: site y takes (1 - omega) fb_i(y + v_i) + rhob(y + v_i) +
+// jb(y + v_i).v_i, with rhob = rhob_loc + rhob_b + Lap^T(lb_tot) and jb of step
+// t computed for the tile and a ring of radius 1 in LDS; the result is
+// written (the next step's C part reads it at neighbours) and used at once as
+// the incoming cotangent of step t - 1.  Fc holds step t's fields, F step
+// t - 1's (rhob_loc and jb are double-buffered by step parity, since other
+// workgroups still read step t's values around their tiles).
+template <int C>
+__global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fbn, double* __restrict__ fbo,
+                                                   Geometry g, Coeffs<C> k, Fields Fc, Fields F) {
+    constexpr int EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2, NT = TX * TY;
+    __shared__ double s_rho[C][EY * EX];
+    __shared__ double s_phi[C][MY * MX];
+    __shared__ double s_rb[C][MY * MX];
+    __shared__ double s_jx[C][MY * MX];
+    __shared__ double s_jy[C][MY * MX];
+    const int N = g.nx * g.ny;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
+    for (int e = threadIdx.x; e < EX * EY; e += NT) {
+        const int ey = e / EX, ex = e - ey * EX;
+        const int s = wrapg(y0 - 2 + ey, g.ny) * g.nx + wrapg(x0 - 2 + ex, g.nx);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_rho[c][e] = F.rho[(int64_t)c * N + s];
+    }
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {  // kernel C's per-site terms of step t, radius 1
+        const int my = m / MX, mx = m - my * MX;
+        const int xx = wrapg(x0 - 1 + mx, g.nx), yy = wrapg(y0 - 1 + my, g.ny);
+        const int e = yy * g.nx + xx;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_rb[c][m] = Fc.rhob_loc[(int64_t)c * N + e] + Fc.rhob_b[(int64_t)c * N + e] +
+                         lapg(Fc.lb_tot + (int64_t)c * N, g, xx, yy);
+            s_jx[c][m] = Fc.jb[(int64_t)(2 * c) * N + e];
+            s_jy[c][m] = Fc.jb[(int64_t)(2 * c + 1) * N + e];
+        }
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        double r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
+            l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
+        }
+        potential<double, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = y * g.nx + x;
+    const double omega = k.omega, cG = k.cG, cL = k.cL;
+
+    // step t's un-streamed cotangent at this site = the incoming cotangent of step t - 1
+    double fin[C][Q];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int q = (ly + 1 + VY[i]) * MX + (lx + 1 + VX[i]);
+            const int src = wrapg(y + VY[i], g.ny) * g.nx + wrapg(x + VX[i], g.nx);
+            const double pb = (1.0 - omega) * fbn[((int64_t)i * g.plane + src) * C + c] + s_rb[c][q] +
+                              s_jx[c][q] * VX[i] + s_jy[c][q] * VY[i];
+            fin[c][i] = pb;
+            fbo[((int64_t)i * g.plane + s) * C + c] = pb;
+        }
+    }
+    double rho[C], jx[C], jy[C], g0x[C], g0y[C], dpx[C], dpy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = F.rho[(int64_t)c * N + s];
+        jx[c] = F.mom[(int64_t)(2 * c) * N + s];
+        jy[c] = F.mom[(int64_t)(2 * c + 1) * N + s];
+        double rx, ry;
+        grad9s<double, MX>(s_phi[c], lx + 1, ly + 1, dpx[c], dpy[c]);
+        grad9s<double, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
+        g0x[c] = -rho[c] * dpx[c];
+        g0y[c] = -rho[c] * dpy[c];
+        if (k.force == 0) {
+            g0x[c] += THETA * rx;
+            g0y[c] += THETA * ry;
+        }
+    }
+    // forward friction (C = 2 closed form)
+    double gx[C], gy[C];
+    double m = 0, K = 0, d0x = 0, d0y = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        gx[c] = g0x[c];
+        gy[c] = g0y[c];
+    }
+    if constexpr (C == 2) {
+        const double lam = k.lam(0, 1);
+        m = rho[0] * rho[1] / (rho[0] + rho[1]);
+        K = lam / (1.0 + 0.5 * lam);
+        d0x = (jx[1] + 0.5 * g0x[1]) / rho[1] - (jx[0] + 0.5 * g0x[0]) / rho[0];
+        d0y = (jy[1] + 0.5 * g0y[1]) / rho[1] - (jy[0] + 0.5 * g0y[0]) / rho[0];
+        gx[0] += K * m * d0x;
+        gx[1] -= K * m * d0x;
+        gy[0] += K * m * d0y;
+        gy[1] -= K * m * d0y;
+    }
+
+    // collision adjoint: h = omega [rho M0 + 3 j.M + Q(j)/rho] + 3 G.M
+    //                        + [2 G.B.j + cG Q(G)]/rho + cL L tr B
+    double rb[C], jbx[C], jby[C], gbx[C], gby[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double M0 = 0, Mx = 0, My = 0, Mxx = 0, Myy = 0, Mxy = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+            const double fb = w * fin[c][i];
+            const double vx = VX[i], vy = VY[i];
+            M0 += fb;
+            Mx += fb * vx;
+            My += fb * vy;
+            Mxx += fb * vx * vx;
+            Myy += fb * vy * vy;
+            Mxy += fb * vx * vy;
+        }
+        const double Bxx = 4.5 * Mxx - 1.5 * M0, Byy = 4.5 * Myy - 1.5 * M0, Bxy = 4.5 * Mxy;
+        const double r = rho[c], ri = 1.0 / r;
+        const double Jx = jx[c], Jy = jy[c], Gx = gx[c], Gy = gy[c];
+        const double Qj = Bxx * Jx * Jx + Byy * Jy * Jy + 2.0 * Bxy * Jx * Jy;
+        const double QG = Bxx * Gx * Gx + Byy * Gy * Gy + 2.0 * Bxy * Gx * Gy;
+        const double BJx = Bxx * Jx + Bxy * Jy, BJy = Bxy * Jx + Byy * Jy;
+        const double BGx = Bxx * Gx + Bxy * Gy, BGy = Bxy * Gx + Byy * Gy;
+        const double GBJ = Gx * BJx + Gy * BJy;
+        rb[c] = omega * (M0 - Qj * ri * ri) - (2.0 * GBJ + cG * QG) * ri * ri;
+        jbx[c] = omega * (3.0 * Mx + 2.0 * BJx * ri) + 2.0 * BGx * ri;
+        jby[c] = omega * (3.0 * My + 2.0 * BJy * ri) + 2.0 * BGy * ri;
+        gbx[c] = 3.0 * Mx + 2.0 * (BJx + cG * BGx) * ri;
+        gby[c] = 3.0 * My + 2.0 * (BJy + cG * BGy) * ri;
+        F.lb[(int64_t)c * N + s] = cL * (Bxx + Byy);
+    }
+    // friction adjoint: G = G0 + (+-) K m d0
+    double g0bx[C], g0by[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        g0bx[c] = gbx[c];
+        g0by[c] = gby[c];
+    }
+    if constexpr (C == 2) {
+        const double gfbx = gbx[0] - gbx[1], gfby = gby[0] - gby[1];
+        const double mb = K * (gfbx * d0x + gfby * d0y);
+        const double dbx = K * m * gfbx, dby = K * m * gfby;
+        const double s2 = (rho[0] + rho[1]) * (rho[0] + rho[1]);
+        rb[0] += mb * rho[1] * rho[1] / s2;
+        rb[1] += mb * rho[0] * rho[0] / s2;
+        // d0 = (j1 + G0_1/2)/rho1 - (j0 + G0_0/2)/rho0, per axis
+        const double i0 = 1.0 / rho[0], i1 = 1.0 / rho[1];
+        jbx[1] += dbx * i1;
+        jbx[0] -= dbx * i0;
+        jby[1] += dby * i1;
+        jby[0] -= dby * i0;
+        g0bx[1] += 0.5 * dbx * i1;
+        g0bx[0] -= 0.5 * dbx * i0;
+        g0by[1] += 0.5 * dby * i1;
+        g0by[0] -= 0.5 * dby * i0;
+        rb[1] -= (dbx * (jx[1] + 0.5 * g0x[1]) + dby * (jy[1] + 0.5 * g0y[1])) * i1 * i1;
+        rb[0] += (dbx * (jx[0] + 0.5 * g0x[0]) + dby * (jy[0] + 0.5 * g0y[0])) * i0 * i0;
+    }
+    // force adjoint, local part: G0 = -rho grad phi (+ theta grad rho)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rb[c] -= g0bx[c] * dpx[c] + g0by[c] * dpy[c];
+        F.rhob_loc[(int64_t)c * N + s] = rb[c];
+        F.jb[(int64_t)(2 * c) * N + s] = jbx[c];
+        F.jb[(int64_t)(2 * c + 1) * N + s] = jby[c];
+        F.av[(int64_t)(2 * c) * N + s] = rho[c] * g0bx[c];
+        F.av[(int64_t)(2 * c + 1) * N + s] = rho[c] * g0by[c];
+        F.bv[(int64_t)(2 * c) * N + s] = k.force == 0 ? g0bx[c] : 0.0;
+        F.bv[(int64_t)(2 * c + 1) * N + s] = k.force == 0 ? g0by[c] : 0.0;
+    }
+}
+
 // Kernel B: potential adjoint and parameter cotangents (one partial vector
 // per workgroup, reduced in a fixed order).
 template <int C>
@@ -413,8 +598,10 @@ adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
     F.rho = mom0;
     F.mom = mom0 + (int64_t)C * L.N;
     double* f = ws + L.fields;
-    F.rhob_loc = f;
-    F.jb = f + (int64_t)C * L.N;
+    // rhob_loc and jb by step parity (the fused kernel reads step t's values
+    // around its tile while it writes step t - 1's)
+    F.rhob_loc = f + ((t & 1) ? 10 * (int64_t)C * L.N : 0);
+    F.jb = f + ((t & 1) ? 11 : 1) * (int64_t)C * L.N;
     F.av = f + 3 * (int64_t)C * L.N;
     F.bv = f + 5 * (int64_t)C * L.N;
     F.lb = f + 7 * (int64_t)C * L.N;
@@ -424,16 +611,65 @@ adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
 }
 
 template <int C>
-hipError_t adjoint_step(const vdwlb_plan& p, const Layout& L, double* ws, int t, const double* fbn, double* fbo,
-                        hipStream_t s) {
-    Geometry g = make_geometry(p, adj::TX, adj::TY);
-    const Coeffs<C> k = make_coeffs<C>(p);
-    adj::Fields F = fields_at(p, L, ws, t);
-    const int tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
-    hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k, F);
-    hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, F,
-                       ws + L.partial + (int64_t)t * L.nb_b * L.np);
-    hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega, F);
+struct StepKernels {
+    const vdwlb_plan& p;
+    const Layout& L;
+    double* ws;
+    hipStream_t s;
+    Geometry g;
+    Coeffs<C> k;
+    int tiles;
+    StepKernels(const vdwlb_plan& p_, const Layout& L_, double* ws_, hipStream_t s_)
+        : p(p_), L(L_), ws(ws_), s(s_), g(make_geometry(p_, adj::TX, adj::TY)), k(make_coeffs<C>(p_)) {
+        tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
+    }
+    void a(int t, const double* fbn) {
+        hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k,
+                           fields_at(p, L, ws, t));
+    }
+    void b(int t) {
+        hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, fields_at(p, L, ws, t),
+                           ws + L.partial + (int64_t)t * L.nb_b * L.np);
+    }
+    void c(int t, const double* fbn, double* fbo) {
+        hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega,
+                           fields_at(p, L, ws, t));
+    }
+    // kernel C of step t + 1 fused with kernel A of step t
+    void ca(int t, const double* fbn, double* fbo) {
+        hipLaunchKernelGGL((adj::k_adj_ca<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
+                           fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t));
+    }
+};
+
+bool adjoint_fused() {
+    const char* v = std::getenv("VDWLB_ADJ_UNFUSED");
+    return !(v && v[0] == '1');
+}
+
+// The reverse sweep of a segment from fbar_io; the result ends in bufs[n & 1].
+// Unfused: per step A, B, C.  Fused: A, B for the last step, then per earlier
+// step the fused C + A and B, and a final C.  Both compute the same values.
+template <int C>
+hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* const (&bufs)[2],
+                         hipStream_t s, bool fused) {
+    StepKernels<C> K(p, L, ws, s);
+    if (!fused) {
+        for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
+            K.a(t, bufs[k & 1]);
+            K.b(t);
+            K.c(t, bufs[k & 1], bufs[(k + 1) & 1]);
+        }
+        return hipGetLastError();
+    }
+    for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
+        if (k == 0)
+            K.a(t, bufs[0]);
+        else
+            K.ca(t, bufs[(k - 1) & 1], bufs[k & 1]);
+        K.b(t);
+    }
+    K.c(0, bufs[(nsteps - 1) & 1], bufs[nsteps & 1]);
     return hipGetLastError();
 }
 
@@ -441,7 +677,7 @@ hipError_t adjoint_step(const vdwlb_plan& p, const Layout& L, double* ws, int t,
 // workspace (keeping each step's moments), then the reverse sweep from
 // fbar_io; the result ends in fbar_io.
 hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* fbar_io,
-                           double* pbar, hipStream_t s) {
+                           double* pbar, hipStream_t s, bool fused) {
     hipError_t e = hipSuccess;
     for (int t = 0; t < nsteps && e == hipSuccess; ++t) {
         double* cur = ws + ((t & 1) ? L.f1 : L.f0);
@@ -449,12 +685,10 @@ hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int
         double* m = ws + L.moms + (int64_t)t * 3 * p.C * L.N;
         e = launch_sweep(p, cur, nxt, s, m);  // the sweep also writes this step's moments
     }
-    double* bufs[2] = {fbar_io, ws + L.fb};
-    for (int t = nsteps - 1, k = 0; t >= 0 && e == hipSuccess; --t, ++k) {
-        const double* fbn = bufs[k & 1];
-        double* fbo = bufs[(k + 1) & 1];
-        e = p.C == 1 ? adjoint_step<1>(p, L, ws, t, fbn, fbo, s) : adjoint_step<2>(p, L, ws, t, fbn, fbo, s);
-    }
+    double* const bufs[2] = {fbar_io, ws + L.fb};
+    if (e == hipSuccess)
+        e = p.C == 1 ? reverse_steps<1>(p, L, ws, nsteps, bufs, s, fused)
+                     : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
     if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
         hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
                            nsteps * L.nb_b, L.np, pbar);
@@ -508,18 +742,20 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
     // does not depend on where the caller keeps its checkpoints
     hipError_t e = hipMemcpyAsync(ws + L.f0, f_ckpt, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return set_device_error(e, "adjoint checkpoint copy");
+    const bool fused = adjoint_fused();
     if (!graphs_enabled()) {
-        e = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, s);
+        e = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, s, fused);
         return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint segment");
     }
     AdjointGraph& G = p->adj;
     if (!(G.exec && G.nsteps == nsteps && G.fbar == fbar_io && G.ws == workspace && G.pbar == pbar_accum &&
-          G.sched == p->sched && G.map_mode == p->map_mode)) {
+          G.sched == p->sched && G.map_mode == p->map_mode && G.fused == fused)) {
         release_adjoint_graph(*p);
         if (!p->capture_stream) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return set_device_error(e, "adjoint capture");
-        const hipError_t le = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, p->capture_stream);
+        const hipError_t le =
+            enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, p->capture_stream, fused);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->capture_stream, &g);
         if (le != hipSuccess || e != hipSuccess || !g) {
@@ -538,6 +774,7 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
         G.pbar = pbar_accum;
         G.sched = p->sched;
         G.map_mode = p->map_mode;
+        G.fused = fused;
     }
     e = hipGraphLaunch(G.exec, s);
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint graph launch");

@@ -12,6 +12,7 @@
 struct AdjointGraph {
     hipGraphExec_t exec = nullptr;
     int nsteps = 0, sched = -1, map_mode = -1;
+    bool fused = true;
     const void *fbar = nullptr, *ws = nullptr, *pbar = nullptr;
 };
 

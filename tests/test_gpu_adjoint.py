@@ -274,3 +274,33 @@ def test_row_schedules_equal_default(gpu, tau):
     for loss, grad in out[1:]:
         assert loss == out[0][0]
         assert np.array_equal(grad, out[0][1])
+
+
+@pytest.mark.parametrize("C,tau", [(2, 1.0), (2, 0.8), (1, 1.0)])
+def test_fused_reverse_equals_unfused(gpu, monkeypatch, C, tau):
+    """The reverse sweep fuses the un-stream of each step with the collision
+    adjoint of the step before (gathering what the separate kernel
+    scatters); loss and gradient must equal the three-kernel sequence, with
+    segments of odd and even length (45 steps, checkpoints every 10) and a
+    one-step segment."""
+    adjoint, _, _ = gpu
+    P = mixture(C, tau=tau)
+    k_hat = P["kappa"] / 0.1
+    nx, ny = 40, 28
+    rng = np.random.default_rng(5)
+    rho0 = (5.25 / C) * (1 + 0.01 * rng.uniform(-1, 1, (C, ny, nx)))
+    tg = torch.as_tensor(rho0[0].mean() * (1 + 0.05 * np.cos(2 * np.pi * np.arange(nx) / nx))[None, :].repeat(ny, 0),
+                         device="cuda")
+    theta = adjoint.theta_from_params(P["kT"], P["a"], P["b"], 0.1)
+    loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
+    r0 = torch.as_tensor(rho0, device="cuda")
+    for nsteps, ckpt in ((45, 10), (1, 1)):
+        spec = adjoint.Spec(nx, ny, C, k_hat, nsteps, ckpt=ckpt, tau=P["tau"], gamma_mu=P["gamma_mu"],
+                            lam=P["lam"])
+        monkeypatch.delenv("VDWLB_ADJ_UNFUSED", raising=False)
+        fused = adjoint.run_and_grad(theta, r0, spec, loss_fn)
+        monkeypatch.setenv("VDWLB_ADJ_UNFUSED", "1")
+        plain = adjoint.run_and_grad(theta, r0, spec, loss_fn)
+        monkeypatch.delenv("VDWLB_ADJ_UNFUSED")
+        assert fused[0] == plain[0]
+        np.testing.assert_allclose(fused[1], plain[1], rtol=1e-13, atol=1e-13 * np.abs(plain[1]).max())
