@@ -9,7 +9,9 @@ value      MLUPS x components (million site updates per second times C), inputs
            resident in HBM, timed with HIP events over exactly --steps steps.
 roofline   the sweep kernel against the 8 TB/s HBM peak, with algorithmic bytes
            2 * 9 * C * sizeof(real) per site update.
-cpu_baseline  the CPU oracle on the host, a bounded sample of the same workload.
+cpu_baseline  the CPU oracle on the host, a bounded sample of the same workload;
+           with the extras also oracle samples beside the batched, adjoint and
+           phase-diagram legs (cpu_baseline.legs).
 extra      the headline's median over 5 separate runs, with init, readback and
            host copies timed on their own; FP32 and 4-component sweeps; the
            batched phase-diagram workload in D2Q9 (strips through L2/MALL) and
@@ -470,8 +472,11 @@ def verification_leg(n=16, steps=50000):
     return out
 
 
-def cpu_baseline(w, steps=8):
-    """The CPU oracle on the same workload for a few steps (single thread)."""
+def cpu_baseline(w, steps=8, seed=0, legs=True):
+    """The CPU oracle on the same workload for a few steps (single thread),
+    and with `legs` bounded samples beside the other GPU legs: the first 32
+    lattices of the batched workload, complex-step gradient directions of the
+    adjoint case, and Appendix A points of the phase-diagram leg."""
     from oracle import oracle as O
 
     lat = O.Lattice(O.Params(w.kT, w.a, w.b, w.kappa, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam), 2, w.nx, w.ny)
@@ -479,7 +484,7 @@ def cpu_baseline(w, steps=8):
     t0 = time.perf_counter()
     lat.run(steps)
     secs = time.perf_counter() - t0
-    return {
+    out = {
         "value": w.nx * w.ny * w.C * steps / secs / 1e6,
         "unit": "MLUPS×C",
         "cores": 1,
@@ -487,6 +492,67 @@ def cpu_baseline(w, steps=8):
         "sample": f"{steps} steps of the same {w.nx}x{w.ny} C={w.C} FP64 workload, single-threaded C oracle",
         "seconds": secs,
     }
+    if legs:
+        out["legs"] = cpu_legs(O, seed)
+    return out
+
+
+def cpu_legs(O, seed):
+    """Single-threaded oracle samples beside the batched, adjoint and
+    phase-diagram legs (each a few seconds)."""
+    import numpy as np
+
+    from oracle import thermo as T
+    from paper_1805_07251_amd import inputs as I
+    from paper_1805_07251_amd import vdwlb as V
+
+    legs = {}
+
+    def maxwell(a, b, kT):
+        try:
+            return V.maxwell(a, b, kT)
+        except V.VdwlbError:
+            return None
+
+    ws = I.batch_slabs(maxwell, seed)[:32]
+    nsteps = 200
+    t0 = time.perf_counter()
+    site_steps = 0
+    for w in ws:
+        lat = O.Lattice(O.Params(w.kT, w.a, w.b, w.kappa, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam), 2, w.nx, w.ny)
+        lat.init(w.rho)
+        lat.run(nsteps)
+        site_steps += w.nx * w.ny * nsteps
+    secs = time.perf_counter() - t0
+    legs["batched"] = {"value": site_steps * ws[0].C / secs / 1e6, "unit": "MLUPS×C", "seconds": secs,
+                       "sample": f"the first 32 lattices of the batched workload, {nsteps} steps each, one after "
+                                 "another"}
+
+    w, _ = I.adjoint_case(seed)
+    p = O.Params(w.kT, w.a, w.b, w.kappa, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
+    nsteps, ndir, h = 10, 7, 1e-20
+    t0 = time.perf_counter()
+    for q in range(ndir):
+        lc = O.Lattice(p, 2, w.nx, w.ny, complex_step=True)
+        d = np.zeros(lc.prm.shape)
+        d[q] = 1.0
+        lc.prm = lc.prm.astype(np.complex128) + 1j * h * d
+        lc.init(w.rho)
+        lc.run(nsteps)
+    secs = time.perf_counter() - t0
+    full = secs / nsteps * 2000
+    legs["adjoint"] = {"seconds": secs, "extrapolated_gradient_seconds": full,
+                       "sample": f"complex-step forward of the 256x256 adjoint case in {ndir} parameter directions, "
+                                 f"{nsteps} steps each; the 2000-step gradient extrapolated linearly"}
+
+    a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
+    pts = [(2.0, 0.5), (1.2, 0.3), (0.8, 0.8)]
+    t0 = time.perf_counter()
+    its = [T.phase_point(NA, NB, 1 / 3, a, b)["iterations"] for NA, NB in pts]
+    secs = time.perf_counter() - t0
+    legs["phase_points"] = {"seconds": secs, "seconds_per_point": secs / len(pts), "iterations": its,
+                            "sample": f"Appendix A pipeline at {pts} of the baseline mixture (Python oracle)"}
+    return legs
 
 
 def main():
@@ -549,7 +615,7 @@ def main():
         extra["verification"] = verification_leg()
     out["extra"] = extra
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, seed=args.seed, legs=not args.no_extra)
     print(json.dumps(out))
 
 
