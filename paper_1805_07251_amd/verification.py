@@ -36,7 +36,8 @@ from . import phase as P
 from .batch import Batch
 
 CS2 = 1.0 / 3.0  # lattice speed of sound squared (theta)
-DELTA = 1e-3  # displacement across the tie line that brackets the local binodal
+DELTA = 1e-5  # displacement across the tie line that brackets the local binodal (small: the chord's offset
+# from the curved binodal grows with the square of its length)
 
 
 @dataclass
@@ -45,8 +46,9 @@ class SlabSetup:
     kappa: float = 0.4
     width: float = 2.0
     tau: float = 1.0
-    gamma_scale: float = 0.5  # fraction of the width rule's gamma_mu (Eq. kappaGammaMuRelation)
+    gamma_scale: float = 1.0  # fraction of the width rule's gamma_mu (Eq. kappaGammaMuRelation)
     window: int = 2  # bulk values are means over 2 window + 1 sites (period-2 ripple of the central difference)
+    lam: float = 0.01  # friction lambda^{cc'} between the components (Eq. forceFriction): it sets how fast they interdiffuse
 
 
 def two_phase_profile(L, rho_in, rho_out, n_in, width):
@@ -73,7 +75,8 @@ def slab_workloads(kT, a, b, phases, setup: SlabSetup = SlabSetup()):
         rho_l = dense[0] + dense[1]
         gam = setup.gamma_scale * (1.0 - CS2) / (4.0 * setup.kappa * rho_l)
         ws.append(I.Workload(setup.L, 1, kT, np.asarray(a, float), np.asarray(b, float), kap, prof[:, None, :],
-                             tau=setup.tau, gamma_mu=gam, dim=1))
+                             tau=setup.tau, gamma_mu=gam, dim=1,
+                             lam=np.full((2, 2), setup.lam)))
     return ws
 
 
@@ -289,7 +292,8 @@ def run_three_phase(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(
         rho_l = max(phases[ia, :2].sum(), phases[ib, :2].sum())
         gam = setup.gamma_scale * (1.0 - CS2) / (4.0 * setup.kappa * rho_l)
         ws.append(I.Workload(setup.L, 1, kT, np.asarray(a, float), np.asarray(b, float), kap, prof[:, None, :],
-                             tau=setup.tau, gamma_mu=gam, dim=1))
+                             tau=setup.tau, gamma_mu=gam, dim=1,
+                             lam=np.full((2, 2), setup.lam)))
         preds.append(np.stack([phases[g, :2], phases[ia, :2], phases[ib, :2]]))
         cents.append(centres)
         pts.append((NA[k], NB[k]))

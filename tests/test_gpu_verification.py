@@ -43,23 +43,25 @@ def test_identical_components_reach_the_binodal(mods):
 
 def test_baseline_mixture_runs(mods):
     """The baseline Type III-H mixture (Fig. graphBaselineCase) on a 12 x 12
-    grid: the gamma_mu search leaves no unphysical run; after 50,000 steps
-    the median distance from the binodal is below 2e-3 (measured: ~1e-3 with
-    kappa = 0.4 on 256 sites; the paper reports mostly 1e-4 with its own,
-    unstated lattice sizes), and running on to 200,000 steps brings the
-    runs closer (material still diffusing between the phases, as the paper
-    notes)."""
+    grid: the gamma_mu search leaves no unphysical run, and after 50,000
+    steps most runs lie within 1e-4 of the binodal and all within 1e-3, the
+    agreement the paper reports (measured: median 1.2e-5, 85 % within 1e-4,
+    max 4e-4 with the friction lambda = 0.01 of the verification setup; with
+    lambda = 1 the components interdiffuse so slowly that the median is still
+    ~8e-4 at 50,000 steps).  The runs are steady: 200,000 steps keep the
+    median within 1e-4."""
     phase, V = mods
     a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
     NA, NB = phase.composition_grid(b, 12)
     r1 = V.run(KT, a, b, NA, NB, steps=50000)
     assert len(r1.status) >= 20 and np.all(r1.status == 0)
-    assert np.all(np.isfinite(r1.deviation))
-    assert np.median(r1.deviation) <= 2e-3
-    assert np.all(r1.deviation <= r1.end_deviation + 1e-5)  # chord vs curve: O(DELTA^2)
+    d = r1.deviation
+    assert np.all(np.isfinite(d))
+    assert np.median(d) <= 1e-4 and np.mean(d <= 1e-4) >= 0.7 and d.max() <= 1e-3, np.sort(d)
+    assert np.all(d <= r1.end_deviation + 1e-6)  # the chord's offset from the curve is O(DELTA^2)
     r2 = V.run(KT, a, b, NA, NB, steps=200000)
     assert np.all(r2.status == 0)
-    assert np.median(r2.deviation) < np.median(r1.deviation)
+    assert np.median(r2.deviation) <= 1e-4
 
 
 def test_interface_width_iteration(mods):
@@ -85,10 +87,10 @@ def test_three_phase_region_runs(mods):
     the paper's largest set of runs): every three-phase point of a 64 x 64
     grid with domains of at least 12 sites is run as gas | A-rich | gas |
     B-rich on 256 sites with kappa = 0.1.  All runs stay physical and their
-    bulk states head for the one three-phase state (Gibbs phase rule): after
-    50,000 steps the median distance is below 5e-3 (measured 3.4e-3; the
-    paper reports ~1e-3 at the binodal intersections), every run is within
-    3e-2, and 200,000 steps bring the median closer."""
+    bulk states reach the one three-phase state (Gibbs phase rule): after
+    50,000 steps the median distance is below 1e-4 (measured 1.4e-5; the
+    paper reports ~1e-3 at the binodal intersections) and every run is
+    within 3e-2; 200,000 steps do not move the median up."""
     phase, V = mods
     a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
     NA, NB = phase.composition_grid(b, 64)
@@ -97,7 +99,7 @@ def test_three_phase_region_runs(mods):
     assert len(r1.status) >= 20 and np.all(r1.status == 0)
     # every point ran from the same three phases (the unique three-phase state)
     assert np.ptp(r1.predicted, axis=0).max() < 1e-10
-    assert np.median(r1.deviation) < 5e-3 and r1.deviation.max() < 3e-2
+    assert np.median(r1.deviation) < 1e-4 and r1.deviation.max() < 3e-2
     r2 = V.run_three_phase(KT, a, b, NA, NB, steps=200000, setup=setup)
     assert np.all(r2.status == 0)
-    assert np.median(r2.deviation) < np.median(r1.deviation)
+    assert np.median(r2.deviation) <= np.median(r1.deviation) * 1.01 + 1e-12
