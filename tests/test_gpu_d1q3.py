@@ -445,22 +445,23 @@ def test_baseline_three_phase_run(gpu):
 
 def test_four_phase_three_component_stress(gpu):
     """The paper's three-component example (Fig. graphLB3Components:
-    theta_cr = 0.5, rho_cr = 1 for all three, nu = 0.05, kappa^{cc} = 2
-    scaled here to 4, theta = 1/3): three nearly pure liquids and a vapour at
-    the four-phase point of the bulk free energy (density ratio ~1250), run
-    for 1,000,000 D1Q3 iterations.  This exercises the C x C implicit
-    friction solve and FP64 stability over a long horizon.
+    theta_cr = 0.5, rho_cr = 1 for all three, nu = 0.05, kappa^{cc} = 2,
+    theta = 1/3): three nearly pure liquids and a vapour at the four-phase
+    point of the bulk free energy (density ratio ~1230), run for 1,000,000
+    D1Q3 iterations.  This exercises the C x C implicit friction solve and
+    FP64 stability over a long horizon.
 
     The paper tuned its parameters by hand for this run and does not print
-    gamma_mu, tau or lambda.  Measured on this implementation with the width
-    rule's gamma_mu every (kappa, tau, lambda) tried became unphysical within
-    about 1e5-4e5 steps; with lambda <= 0.01 and gamma_mu at 0.1-0.25 of the
-    rule the runs stay physical beyond 2e6 steps, with bulk chemical
-    potentials uniform only to ~5e-3 by then (the paper reports 1e-5 after
-    its tuning).  The test uses one such setting and checks: physical for
-    1e6 steps, all four phases still present with their character (each
-    liquid rich in its own component, ratio > 1000), and bulk phases within
-    5e-2 of the four-phase point."""
+    gamma_mu, tau or lambda.  A batched search over kappa in {2, 4, 8},
+    gamma_mu at 0.1-0.4 of the width rule, lambda in {0.01, 0.001}, tau in
+    {0.8, 1} and domains of 80 or 120 sites found this setting best: gamma_mu
+    at 0.4 of the rule, lambda = 0.001, tau = 0.8, 80-site domains, with
+    bulk chemical potentials equal to ~3e-4 and the bulk phases ~1e-3 from
+    the four-phase point after 1e6 steps (the paper reports 1e-5 in mu after
+    its tuning).  Checked: physical for 1e6 steps, all four phases present
+    with their character (each liquid rich in its own component, ratio
+    > 1000), bulk phases within 5e-3 of the four-phase point and bulk mu^c
+    equal to 2e-3."""
     batch, _ = gpu
     from paper_1805_07251_amd.inputs import Workload
 
@@ -475,7 +476,7 @@ def test_four_phase_three_component_stress(gpu):
     pts, res = T.coexistence_invariant_point(start, kT, a, b)
     assert res < 1e-12
     gas, liqs = pts[0], pts[1:]
-    K = 4.0
+    K = 2.0
     kap = np.full((3, 3), nu * K)
     np.fill_diagonal(kap, K)
     D = 80
@@ -486,8 +487,8 @@ def test_four_phase_three_component_stress(gpu):
     prof = np.tile(gas[:, None], (1, L))
     for i in range(3):  # gas | A | gas | B | gas | C
         prof = prof + (liqs[i] - gas)[:, None] * box((2 * i + 1) * D, (2 * i + 2) * D)[None, :]
-    gam = 0.1 * T.gamma_from_width_rule(K, rl)
-    w = Workload(L, 1, kT, a, b, kap, prof[:, None, :], gamma_mu=gam, tau=0.9, lam=np.full((3, 3), 0.01), dim=1)
+    gam = 0.4 * T.gamma_from_width_rule(K, rl)
+    w = Workload(L, 1, kT, a, b, kap, prof[:, None, :], gamma_mu=gam, tau=0.8, lam=np.full((3, 3), 0.001), dim=1)
     bt = batch_run(batch, [w], [1000000])
     assert bt.status()[0] == 0
     r = np_(bt.densities()[0])[:, 0]
@@ -495,14 +496,17 @@ def test_four_phase_three_component_stress(gpu):
     bulk = [window_mean(r, c) for c in centres]
     theory = [gas, liqs[0], gas, liqs[1], gas, liqs[2]]
     dev = max(float(np.abs(g / t - 1).max()) for g, t in zip(bulk, theory))
-    print(f"four-phase run: ratio {r.max() / r.min():.0f}, bulk vs four-phase point {dev:.1e}")
+    mus = np.array([T.chemical_potential(v, kT, a, b) for v in bulk])
+    print(f"four-phase run: ratio {r.max() / r.min():.0f}, bulk vs four-phase point {dev:.1e}, "
+          f"bulk mu ptp {np.ptp(mus, 0).max():.1e}")
     for i in range(3):
         liq = bulk[2 * i + 1]
         assert liq[i] > 2.0 and np.delete(liq, i).max() < 0.01
     for k in (0, 2, 4):
         assert bulk[k].sum() < 0.5
     assert r.max() / r.min() > 1000
-    assert dev < 5e-2
+    assert dev < 5e-3
+    assert np.ptp(mus, 0).max() < 2e-3
 
 
 def test_nid_versus_log_forcing(gpu):
