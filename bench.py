@@ -455,6 +455,24 @@ def verification_leg(n=16, steps=50000):
                                    "deviation_median": float(np.median(r.deviation[ok])),
                                    "deviation_p90": float(np.percentile(r.deviation[ok], 90)),
                                    "deviation_max": float(r.deviation[ok].max())}
+    import csv
+
+    with open(os.path.join(ROOT, "tests", "golden", "vks_captions.csv")) as fh:
+        rows = list(csv.DictReader(line for line in fh if not line.startswith("#")))
+    caps = {}
+    t0 = time.perf_counter()
+    for row in rows:  # the mixtures printed in the figure captions of Sec. VI.A
+        a, b = I.binary_mixture(float(row["theta_cr_a"]), float(row["theta_cr_b"]), 1.0, float(row["rho_cr_b"]),
+                                float(row["nu"]))
+        NA, NB = phase.composition_grid(b, n)
+        r = VV.run(1 / 3, a, b, NA, NB, steps=steps)
+        ok = r.status == 0
+        d = r.deviation[ok]
+        d = d[np.isfinite(d)]
+        caps[row["label"]] = {"runs": int(len(r.status)), "unphysical": int((~ok).sum()),
+                              "deviation_median": float(np.median(d)) if d.size else None,
+                              "deviation_p90": float(np.percentile(d, 90)) if d.size else None}
+    out["captions"] = {"grid": n, "steps": steps, "seconds": time.perf_counter() - t0, "mixtures": caps}
     for name, nu, wi in (("baseline", 0.5, 0), ("identical", 1.0, 0), ("baseline_width_iterated", 0.5, 1)):
         a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, nu)
         NA, NB = phase.composition_grid(b, n)
