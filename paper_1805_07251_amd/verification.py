@@ -62,10 +62,11 @@ def two_phase_profile(L, rho_in, rho_out, n_in, width):
     return rout[:, None] + (rin - rout)[:, None] * s[None, :]
 
 
-def slab_workloads(kT, a, b, phases, setup: SlabSetup = SlabSetup()):
-    """One D1Q3 Workload per two-phase point: phases[k] = ((rA, rB, V), (rA,
-    rB, V)) of the point's distinct phases; the denser phase is the slab,
-    sized by its volume fraction (lever rule)."""
+def slab_workloads(kT, a, b, phases, setup: SlabSetup = SlabSetup(), dim=1):
+    """One Workload per two-phase point: phases[k] = ((rA, rB, V), (rA, rB,
+    V)) of the point's distinct phases; the denser phase is the slab, sized
+    by its volume fraction (lever rule).  dim = 1: a D1Q3 line of L sites;
+    dim = 2: a D2Q9 lattice of L x 4 sites uniform in y."""
     kap = I.kappa_matrix(np.asarray(a, float), setup.kappa)
     ws = []
     for (p0, p1) in phases:
@@ -74,8 +75,9 @@ def slab_workloads(kT, a, b, phases, setup: SlabSetup = SlabSetup()):
         prof = two_phase_profile(setup.L, dense[:2], light[:2], n_in, setup.width)
         rho_l = dense[0] + dense[1]
         gam = setup.gamma_scale * (1.0 - CS2) / (4.0 * setup.kappa * rho_l)
-        ws.append(I.Workload(setup.L, 1, kT, np.asarray(a, float), np.asarray(b, float), kap, prof[:, None, :],
-                             tau=setup.tau, gamma_mu=gam, dim=1,
+        ny = 1 if dim == 1 else 4
+        ws.append(I.Workload(setup.L, ny, kT, np.asarray(a, float), np.asarray(b, float), kap,
+                             np.repeat(prof[:, None, :], ny, axis=1), tau=setup.tau, gamma_mu=gam, dim=dim,
                              lam=np.full((2, 2), setup.lam)))
     return ws
 
@@ -123,7 +125,7 @@ def _matched(meas, ends):
 
 
 def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=200000, gamma_halvings=4,
-        width_iterations=0):
+        width_iterations=0, dim=1):
     """Phase-diagram points (NA, NB) -> minimiser on the GPU -> one D1Q3 slab
     per polished two-phase point -> `steps` lattice Boltzmann steps in one
     batched launch -> bulk states against the binodal.
@@ -136,7 +138,9 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
     Interface-width iteration (Sec. VI.A): `width_iterations` times, the
     equilibrium width of each run's interfaces is measured and the run is
     started again from tanh profiles at the minimiser's bulk values with
-    that width (and the gamma_mu it ended with)."""
+    that width (and the gamma_mu it ended with).
+
+    dim = 2 runs the same slabs as L x 4 D2Q9 lattices (the 2-D extension)."""
     res = P.phase_points(kT, a, b, NA, NB, max_iter=max_iter)
     torch.cuda.synchronize()
     st = res["status"].cpu().numpy()
@@ -146,7 +150,7 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
     if keep.size == 0:
         raise ValueError("no polished two-phase point among the compositions")
     pairs = [(tuple(ph[k, 0]), tuple(ph[k, 1])) for k in keep]
-    ws = slab_workloads(kT, a, b, pairs, setup)
+    ws = slab_workloads(kT, a, b, pairs, setup, dim)
     m = len(ws)
     status = np.full(m, -1, dtype=np.int32)
     dens = [None] * m
@@ -162,7 +166,8 @@ def run(kT, a, b, NA, NB, steps=50000, setup: SlabSetup = SlabSetup(), max_iter=
                 p0, p1 = pairs[j]
                 dense, light = (p0, p1) if p0[0] + p0[1] >= p1[0] + p1[1] else (p1, p0)
                 n_in = int(np.clip(round(dense[2] * setup.L), 8, setup.L - 8))
-                ws[j].rho = two_phase_profile(setup.L, dense[:2], light[:2], n_in, widths[j])[:, None, :]
+                prof = two_phase_profile(setup.L, dense[:2], light[:2], n_in, widths[j])
+                ws[j].rho = np.repeat(prof[:, None, :], ws[j].ny, axis=1)
         todo = np.arange(m)
         for round_ in range(gamma_halvings + 1):
             sub = [ws[j] for j in todo]
