@@ -60,7 +60,7 @@ typedef int32_t vdwlb_status;
 enum {
     VDWLB_OK = 0,
     VDWLB_E_INVALID_ARG = 1, /* a NULL pointer, a bad size or a parameter outside its domain */
-    VDWLB_E_UNSUPPORTED = 2, /* a valid request this build does not implement (dim, C, dtype) */
+    VDWLB_E_UNSUPPORTED = 2, /* a valid request the library does not implement (dim, C, dtype) */
     VDWLB_E_DEVICE = 3,      /* a HIP runtime error; vdwlb_last_device_error() has its text */
     VDWLB_E_UNPHYSICAL = 4   /* the sticky device flag: rho^c <= 0, eta >= 1 or a non-finite value */
 };
