@@ -51,6 +51,8 @@ def parse():
                     help="with --profile: use this sweep schedule instead of autotuning")
     ap.add_argument("--phase", action="store_true",
                     help="profiling run: the 256 x 256 Appendix A phase-diagram leg only")
+    ap.add_argument("--legs", default="",
+                    help="profiling run: only these comma-separated legs (" + ", ".join(LEGS) + ")")
     return ap.parse_args()
 
 
@@ -573,10 +575,34 @@ def cpu_legs(O, seed):
     return legs
 
 
+def _inputs():
+    from paper_1805_07251_amd import inputs as I
+
+    return I
+
+
+# The legs besides the headline, by name (each takes the parsed arguments).
+LEGS = {
+    "spinodal_2048_f32": lambda a: sweep_line(_inputs().spinodal_large(a.seed, dtype="f32"), "f32", a.steps,
+                                              a.warmup),
+    "mixture4_1024_f32": lambda a: sweep_line(_inputs().mixture4(a.seed), "f32", 5000, a.warmup),
+    "batched": lambda a: batch_leg(a.seed, 20000, 10),
+    "d1q3_line_16M_f64": lambda a: sweep_line(_inputs().line_spinodal(a.seed, L=1 << 24), "f64", 2000, a.warmup),
+    "batched_d1q3": lambda a: batch_d1q3_leg(a.seed, 50000),
+    "adjoint": lambda a: adjoint_leg(a.seed),
+    "copy": lambda a: {"gbs": copy_gbs(reps=5), "bytes": 1 << 30},
+}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sweep is not sharded.", file=sys.stderr)
+        sys.exit(2)
+    names = [n for n in args.legs.split(",") if n]
+    unknown = [n for n in names if n not in LEGS]
+    if unknown:
+        print(f"unknown legs {unknown}; choose from {list(LEGS)}", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -585,6 +611,13 @@ def main():
     torch.cuda.set_device(0)
     if args.phase:
         print(json.dumps({"profile": True, "phase_diagram_256": phase_diagram_leg()}))
+        return
+    if args.legs:
+        out = {"profile": True}
+        for n in names:
+            out[n] = LEGS[n](args)
+            print(f"leg {n} done", file=sys.stderr, flush=True)
+        print(json.dumps(out))
         return
     w = I.spinodal_large(args.seed)
     head = sweep_line(w, "f64", args.steps, args.warmup, args.schedule if args.profile else -1)
@@ -620,15 +653,11 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["headline_protocol"] = protocol_leg(w, "f64", head["schedule"])
-        extra["spinodal_2048_f32"] = sweep_line(I.spinodal_large(args.seed, dtype="f32"), "f32", args.steps,
-                                                args.warmup)
-        w2 = I.mixture4(args.seed)
-        extra["mixture4_1024_f32"] = sweep_line(w2, "f32", 5000, args.warmup)
+        for n in ("spinodal_2048_f32", "mixture4_1024_f32"):
+            extra[n] = LEGS[n](args)
         extra["copy_kernel_gbs"] = copy_gbs()
-        extra["batched"] = batch_leg(args.seed, 20000, 10)
-        extra["d1q3_line_16M_f64"] = sweep_line(I.line_spinodal(args.seed, L=1 << 24), "f64", 2000, args.warmup)
-        extra["batched_d1q3"] = batch_d1q3_leg(args.seed, 50000)
-        extra["adjoint"] = adjoint_leg(args.seed)
+        for n in ("batched", "d1q3_line_16M_f64", "batched_d1q3", "adjoint"):
+            extra[n] = LEGS[n](args)
         extra["phase_diagram_256"] = phase_diagram_leg()
         extra["verification"] = verification_leg()
     out["extra"] = extra
