@@ -185,7 +185,8 @@ vdwlb_status vdwlb_set_schedule(vdwlb_plan* plan, int32_t k);
 
 /* Time every schedule on this plan's lattice (reads fA, overwrites fB),
  * re-time the four fastest with more launches, keep the fastest and report it
- * in *chosen (may be NULL).  Synchronous. */
+ * in *chosen (may be NULL).  Synchronous.  fA may hold any state: the error
+ * flag read by vdwlb_sync_status is left as it was before the call. */
 vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* stream, int32_t* chosen);
 
 /* Liquid-gas coexistence of one van der Waals component (Eqs. tetcr, rhocr

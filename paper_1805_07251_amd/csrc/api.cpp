@@ -214,6 +214,12 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     if (!p || !fA || !fB || fA == fB) return VDWLB_E_INVALID_ARG;
     if (!state_aligned(*p, fA) || !state_aligned(*p, fB)) return VDWLB_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    // The timing sweeps run on whatever fA holds and may raise the error flag;
+    // the flag is restored afterwards so that it still describes the caller's
+    // own steps.
+    int keep_flag = 0;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(&keep_flag, p->d_flag, sizeof keep_flag, hipMemcpyDeviceToHost));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -252,6 +258,8 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
             e = time_k(t[j].second, 4 * reps, ms);
             acc[j] += ms;
         }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(p->d_flag, &keep_flag, sizeof keep_flag, hipMemcpyHostToDevice);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_graph(*p);

@@ -170,7 +170,8 @@ class Lattice:
         return int(V.lib().vdwlb_sync_status(self.plan.handle, _stream_ptr(stream)))
 
     def autotune(self, stream=None) -> int:
-        """Pick the fastest tile schedule (clobbers the spare buffer only)."""
+        """Pick the fastest tile schedule (clobbers the spare buffer only; the
+        error flag keeps the state it had before the call)."""
         k = ctypes.c_int32()
         V.check(V.lib().vdwlb_autotune(self.plan.handle, self.buf[self.cur].data_ptr(),
                                        self.buf[1 - self.cur].data_ptr(), _stream_ptr(stream), ctypes.byref(k)),

@@ -244,6 +244,29 @@ def test_unphysical_state_is_flagged(gpu):
     assert ei.value.status == V.E_UNPHYSICAL
 
 
+def test_autotune_keeps_the_error_flag(gpu):
+    """The autotuner's timing sweeps run on whatever the state holds: over a
+    zeroed state (rho = 0, unphysical) they leave no flag behind for the
+    caller's next steps, and a flag the caller's own steps raised before the
+    call is still reported after it."""
+    from paper_1805_07251_amd import vdwlb as V
+
+    w = I.spinodal_small(3, n=64)
+    lat = gpu.Lattice.from_workload(w)
+    for b in lat.buf:
+        b.zero_()
+    lat.autotune()
+    lat.init(w.rho)
+    lat.run(5)
+    assert lat.status() == V.OK
+    for b in lat.buf:
+        b.zero_()
+    lat.run(1)
+    lat.autotune()
+    assert lat.status() == V.E_UNPHYSICAL
+    assert lat.status() == V.OK
+
+
 def test_invalid_arguments(gpu):
     from paper_1805_07251_amd import vdwlb as V
 
@@ -312,9 +335,31 @@ def test_spinodal_large_f64_sampled(gpu, orc):
     np.testing.assert_allclose(rho.sum(axis=(1, 2)), m0, rtol=1e-12)
 
 
+def test_spinodal_large_f32_sampled(gpu, orc):
+    """2048x2048 FP32 under the schedule the autotuner picks (the benchmark's
+    FP32 leg): 5 steps, sampled sites against the FP64 oracle within the FP32
+    bound, and mass conservation to FP32 accumulation accuracy."""
+    w = I.spinodal_large(0, dtype="f32")
+    lat = gpu.Lattice.from_workload(w)
+    lat.init(w.rho)
+    m0 = np_(lat.moments(False, False)[0]).astype(np.float64).sum(axis=(1, 2))
+    lat.autotune()
+    lat.init(w.rho)
+    lat.run(5)
+    rho = np_(lat.moments(False, False)[0])
+    for x, y in [(0, 0), (2047, 2047), (0, 2047), (2047, 5), (1000, 1333)]:
+        ref = window_rho(orc, w, x, y, 5)
+        assert np.abs(rho[:, y, x] - ref).max() <= 2e-6 * np.abs(ref).max(), (x, y)
+    np.testing.assert_allclose(rho.astype(np.float64).sum(axis=(1, 2)), m0, rtol=1e-5)
+
+
 def test_mixture4_f32_sampled(gpu, orc):
+    """1024x1024, 4 components, FP32 under the autotuned schedule (the
+    benchmark's C = 4 leg): 5 steps, sampled sites against the oracle."""
     w = I.mixture4(0)
     lat = gpu.Lattice.from_workload(w)
+    lat.init(w.rho)
+    lat.autotune()
     lat.init(w.rho)
     lat.run(5)
     rho = np_(lat.moments(False, False)[0])
