@@ -58,12 +58,13 @@ int32_t validate_desc(const vdwlb_desc* d) {
     for (int c = 0; c < C; ++c) {
         if (!(d->b[c] > 0) || !is_finite(d->b[c])) return VDWLB_E_INVALID_ARG;
         for (int e = 0; e < C; ++e) {
-            const double a = d->a[c * C + e], k = d->kappa[c * C + e];
+            const int64_t ce = (int64_t)c * C + e, ec = (int64_t)e * C + c;
+            const double a = d->a[ce], k = d->kappa[ce];
             if (!is_finite(a) || !is_finite(k)) return VDWLB_E_INVALID_ARG;
-            if (a != d->a[e * C + c] || k != d->kappa[e * C + c]) return VDWLB_E_INVALID_ARG;
+            if (a != d->a[ec] || k != d->kappa[ec]) return VDWLB_E_INVALID_ARG;
             if (d->lambda) {
-                const double l = d->lambda[c * C + e];
-                if (c != e && (!is_finite(l) || l < 0 || l != d->lambda[e * C + c])) return VDWLB_E_INVALID_ARG;
+                const double l = d->lambda[ce];
+                if (c != e && (!is_finite(l) || l < 0 || l != d->lambda[ec])) return VDWLB_E_INVALID_ARG;
             }
         }
     }
