@@ -355,6 +355,25 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* plan, const void* rho_bar, const 
 vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
                                    void* workspace, double* pbar_accum, void* stream);
 
+/* The two halves of vdwlb_adjoint_segment, for callers that overlap the
+ * forward recompute of one segment with the reverse sweep of the next one on
+ * a second stream (the recompute depends only on its checkpoint), each half
+ * with its own workspace.
+ *
+ * vdwlb_adjoint_recompute: copies f_ckpt into the workspace and recomputes
+ * nsteps forward steps from it, keeping their densities and momenta in the
+ * workspace.  vdwlb_adjoint_reverse: the reverse sweep of the segment last
+ * recomputed into the same workspace with the same nsteps (the caller orders
+ * the two, by stream or event); it replaces fbar_io and adds to pbar_accum
+ * exactly as vdwlb_adjoint_segment does, which is the recompute followed by
+ * the reverse sweep on one stream.  A workspace must not be recomputed into
+ * while a reverse sweep that reads it may still run.  Asynchronous on
+ * stream; arguments and errors as for vdwlb_adjoint_segment. */
+vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* workspace,
+                                     void* stream);
+vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* plan, int32_t nsteps, void* fbar_io, void* workspace,
+                                   double* pbar_accum, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

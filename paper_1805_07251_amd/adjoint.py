@@ -11,6 +11,7 @@ density field rho^c [C, ny, nx] of the final state.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -106,10 +107,13 @@ class VdwLBFunction(torch.autograd.Function):
         npar = int(V.lib().vdwlb_adjoint_param_count(plan.handle))
         pbar = torch.zeros(npar, dtype=torch.float64, device=dev)
         ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(ctx.segs)))
-        ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
-        for ck, m in zip(reversed(ctx.ckpts), reversed(ctx.segs)):
-            V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(), ws.data_ptr(),
-                                                  pbar.data_ptr(), s), "vdwlb_adjoint_segment")
+        if len(ctx.segs) > 1 and os.environ.get("VDWLB_ADJ_SERIAL") != "1":
+            _reverse_overlapped(plan, ctx.ckpts, ctx.segs, fbar, pbar, ws_bytes, dev)
+        else:
+            ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
+            for ck, m in zip(reversed(ctx.ckpts), reversed(ctx.segs)):
+                V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(),
+                                                      ws.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_segment")
         g = pbar.cpu().numpy()
         C = spec.C
         pairs = theta_layout(C)
@@ -118,6 +122,43 @@ class VdwLBFunction(torch.autograd.Function):
         dkappa = sum(g[1 + na + C + q] * k_hat[c, d] for q, (c, d) in enumerate(pairs))
         grad = np.concatenate([g[:1 + na + C], [dkappa]])
         return torch.as_tensor(grad, dtype=ctx.theta_dtype, device=ctx.theta_device), None, None
+
+
+def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev):
+    """Reverse the segments from the last to the first with the forward
+    recompute of segment k - 1 on a second stream, into a second workspace,
+    while the reverse sweep of segment k runs on the current stream.  The
+    reverse sweeps run in the same order on one stream as the one-stream
+    loop, so the results are the same bit for bit."""
+    lib = V.lib()
+    main = torch.cuda.current_stream(dev)
+    aux = torch.cuda.Stream(device=dev)
+    ws = [torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev) for _ in range(2)]
+    aux.wait_stream(main)  # checkpoints and workspaces are ready
+    freed = [None, None]  # per workspace: the end of the last reverse sweep that reads it
+
+    def recompute(k):
+        j = k % 2
+        if freed[j] is not None:
+            aux.wait_event(freed[j])
+        V.check(lib.vdwlb_adjoint_recompute(plan.handle, ckpts[k].data_ptr(), int(segs[k]), ws[j].data_ptr(),
+                                            aux.cuda_stream), "vdwlb_adjoint_recompute")
+        ev = torch.cuda.Event()
+        ev.record(aux)
+        return ev
+
+    ready = recompute(len(segs) - 1)
+    for k in range(len(segs) - 1, -1, -1):
+        nxt = recompute(k - 1) if k > 0 else None
+        main.wait_event(ready)
+        V.check(lib.vdwlb_adjoint_reverse(plan.handle, int(segs[k]), fbar.data_ptr(), ws[k % 2].data_ptr(),
+                                          pbar.data_ptr(), main.cuda_stream), "vdwlb_adjoint_reverse")
+        ev = torch.cuda.Event()
+        ev.record(main)
+        freed[k % 2] = ev
+        ready = nxt
+    # every use of the workspaces on the second stream ends before the last
+    # reverse sweep starts, so the current stream may reuse their memory
 
 
 def run_and_grad(theta, rho0, spec: Spec, loss_fn):

@@ -555,8 +555,9 @@ __global__ void __launch_bounds__(BLK) k_moments_adj(const double* __restrict__ 
 using namespace vdwlb;
 
 void vdwlb::release_adjoint_graph(vdwlb_plan& p) {
-    if (p.adj.exec) (void)hipGraphExecDestroy(p.adj.exec);
-    p.adj = AdjointGraph{};
+    for (AdjointGraph& G : p.adj)
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    p.adj.clear();
 }
 
 namespace {
@@ -674,10 +675,8 @@ hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int n
 }
 
 // Forward recompute of a segment from the checkpoint already in the
-// workspace (keeping each step's moments), then the reverse sweep from
-// fbar_io; the result ends in fbar_io.
-hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* fbar_io,
-                           double* pbar, hipStream_t s, bool fused) {
+// workspace, keeping each step's moments.
+hipError_t enqueue_recompute(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (int t = 0; t < nsteps && e == hipSuccess; ++t) {
         double* cur = ws + ((t & 1) ? L.f1 : L.f0);
@@ -685,10 +684,16 @@ hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int
         double* m = ws + L.moms + (int64_t)t * 3 * p.C * L.N;
         e = launch_sweep(p, cur, nxt, s, m);  // the sweep also writes this step's moments
     }
+    return e;
+}
+
+// The reverse sweep of a recomputed segment from fbar_io and the segment's
+// parameter cotangents; the result ends in fbar_io.
+hipError_t enqueue_reverse(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* fbar_io,
+                           double* pbar, hipStream_t s, bool fused) {
     double* const bufs[2] = {fbar_io, ws + L.fb};
-    if (e == hipSuccess)
-        e = p.C == 1 ? reverse_steps<1>(p, L, ws, nsteps, bufs, s, fused)
-                     : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
+    hipError_t e = p.C == 1 ? reverse_steps<1>(p, L, ws, nsteps, bufs, s, fused)
+                            : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
     if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
         hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
                            nsteps * L.nb_b, L.np, pbar);
@@ -697,6 +702,63 @@ hipError_t enqueue_segment(const vdwlb_plan& p, const Layout& L, double* ws, int
     if (e == hipSuccess && (nsteps & 1))
         e = hipMemcpyAsync(fbar_io, ws + L.fb, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
     return e;
+}
+
+// Replays the captured graph of `key` (capturing it on first use) on stream s,
+// or launches eagerly when graphs are switched off.  Holds at most six graphs
+// per plan: the recompute and reverse graphs of two workspaces for the full
+// segment length and for a shorter last segment.
+template <typename Enqueue>
+vdwlb_status run_part(vdwlb_plan& p, const AdjointGraph& key, hipStream_t s, Enqueue enqueue, const char* what) {
+    if (!graphs_enabled()) {
+        const hipError_t e = enqueue(s);
+        return e == hipSuccess ? VDWLB_OK : set_device_error(e, what);
+    }
+    AdjointGraph* G = nullptr;
+    for (AdjointGraph& c : p.adj)
+        if (c.exec && c.kind == key.kind && c.nsteps == key.nsteps && c.ws == key.ws && c.fbar == key.fbar &&
+            c.pbar == key.pbar && c.sched == key.sched && c.map_mode == key.map_mode && c.fused == key.fused)
+            G = &c;
+    hipError_t e = hipSuccess;
+    if (!G) {
+        if (!p.capture_stream) e = hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return set_device_error(e, what);
+        const hipError_t le = enqueue(p.capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p.capture_stream, &g);
+        if (le != hipSuccess || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return set_device_error(le != hipSuccess ? le : e, what);
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return set_device_error(e, what);
+        if (p.adj.size() >= 6) {  // drop the oldest, once no launch of it can still be running
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return set_device_error(e, what);
+            }
+            (void)hipGraphExecDestroy(p.adj.front().exec);
+            p.adj.erase(p.adj.begin());
+        }
+        p.adj.push_back(key);
+        G = &p.adj.back();
+        G->exec = exec;
+    }
+    e = hipGraphLaunch(G->exec, s);
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, what);
+}
+
+vdwlb_status check_adjoint(const vdwlb_plan* p, int32_t nsteps, const void* workspace) {
+    if (!p || !workspace || nsteps < 1) return VDWLB_E_INVALID_ARG;
+    if (!state_aligned(*p, workspace)) return VDWLB_E_INVALID_ARG;
+    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+    const Layout L = layout(*p, nsteps);
+    if ((int64_t)nsteps * L.nb_b > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
+    return VDWLB_OK;
 }
 
 }  // namespace
@@ -728,56 +790,60 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const voi
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, "moments adjoint");
 }
 
-vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io, void* workspace,
-                                   double* pbar_accum, void* stream) {
-    if (!p || !f_ckpt || !fbar_io || !workspace || !pbar_accum || nsteps < 1) return VDWLB_E_INVALID_ARG;
-    if (!state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io) || !state_aligned(*p, workspace))
-        return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* workspace,
+                                     void* stream) {
+    vdwlb_status st = check_adjoint(p, nsteps, workspace);
+    if (st != VDWLB_OK) return st;
+    if (!f_ckpt || !state_aligned(*p, f_ckpt)) return VDWLB_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     const Layout L = layout(*p, nsteps);
-    if ((int64_t)nsteps * L.nb_b > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
     double* ws = (double*)workspace;
-    // the checkpoint goes into the workspace eagerly, so a captured segment
+    // the checkpoint goes into the workspace eagerly, so a captured recompute
     // does not depend on where the caller keeps its checkpoints
-    hipError_t e = hipMemcpyAsync(ws + L.f0, f_ckpt, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
+    const hipError_t e =
+        hipMemcpyAsync(ws + L.f0, f_ckpt, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return set_device_error(e, "adjoint checkpoint copy");
-    const bool fused = adjoint_fused();
-    if (!graphs_enabled()) {
-        e = enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, s, fused);
-        return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint segment");
-    }
-    AdjointGraph& G = p->adj;
-    if (!(G.exec && G.nsteps == nsteps && G.fbar == fbar_io && G.ws == workspace && G.pbar == pbar_accum &&
-          G.sched == p->sched && G.map_mode == p->map_mode && G.fused == fused)) {
-        release_adjoint_graph(*p);
-        if (!p->capture_stream) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return set_device_error(e, "adjoint capture");
-        const hipError_t le =
-            enqueue_segment(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, p->capture_stream, fused);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(p->capture_stream, &g);
-        if (le != hipSuccess || e != hipSuccess || !g) {
-            if (g) (void)hipGraphDestroy(g);
-            return set_device_error(le != hipSuccess ? le : e, "adjoint capture");
-        }
-        e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            G.exec = nullptr;
-            return set_device_error(e, "adjoint graph instantiate");
-        }
-        G.nsteps = nsteps;
-        G.fbar = fbar_io;
-        G.ws = workspace;
-        G.pbar = pbar_accum;
-        G.sched = p->sched;
-        G.map_mode = p->map_mode;
-        G.fused = fused;
-    }
-    e = hipGraphLaunch(G.exec, s);
-    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint graph launch");
+    AdjointGraph key;
+    key.kind = 0;
+    key.nsteps = nsteps;
+    key.ws = workspace;
+    key.sched = p->sched;
+    key.map_mode = p->map_mode;
+    return run_part(
+        *p, key, s, [&](hipStream_t cs) { return enqueue_recompute(*p, L, ws, nsteps, cs); }, "adjoint recompute");
+}
+
+vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* p, int32_t nsteps, void* fbar_io, void* workspace,
+                                   double* pbar_accum, void* stream) {
+    vdwlb_status st = check_adjoint(p, nsteps, workspace);
+    if (st != VDWLB_OK) return st;
+    if (!fbar_io || !pbar_accum || !state_aligned(*p, fbar_io)) return VDWLB_E_INVALID_ARG;
+    const Layout L = layout(*p, nsteps);
+    double* ws = (double*)workspace;
+    AdjointGraph key;
+    key.kind = 1;
+    key.nsteps = nsteps;
+    key.ws = workspace;
+    key.fbar = fbar_io;
+    key.pbar = pbar_accum;
+    key.fused = adjoint_fused();
+    return run_part(
+        *p, key, (hipStream_t)stream,
+        [&](hipStream_t cs) {
+            return enqueue_reverse(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, cs, key.fused);
+        },
+        "adjoint reverse");
+}
+
+vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io, void* workspace,
+                                   double* pbar_accum, void* stream) {
+    vdwlb_status st = check_adjoint(p, nsteps, workspace);
+    if (st != VDWLB_OK) return st;
+    if (!f_ckpt || !fbar_io || !pbar_accum || !state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io))
+        return VDWLB_E_INVALID_ARG;
+    st = vdwlb_adjoint_recompute(p, f_ckpt, nsteps, workspace, stream);
+    if (st != VDWLB_OK) return st;
+    return vdwlb_adjoint_reverse(p, nsteps, fbar_io, workspace, pbar_accum, stream);
 }
 
 }  // extern "C"

@@ -8,9 +8,11 @@
 
 #include "../../include/vdwlb.h"
 
-// Captured adjoint segment, bound to its step count, buffers and schedule.
+// Captured part of an adjoint segment (the forward recompute or the reverse
+// sweep), bound to its step count, buffers and schedule.
 struct AdjointGraph {
     hipGraphExec_t exec = nullptr;
+    int kind = 0;  // 0: recompute, 1: reverse sweep
     int nsteps = 0, sched = -1, map_mode = -1;
     bool fused = true;
     const void *fbar = nullptr, *ws = nullptr, *pbar = nullptr;
@@ -30,7 +32,7 @@ struct vdwlb_plan {
     const void* gA = nullptr;
     const void* gB = nullptr;
     hipStream_t capture_stream = nullptr;
-    AdjointGraph adj;
+    std::vector<AdjointGraph> adj;  // captured recompute / reverse graphs of up to two workspaces
 };
 
 namespace vdwlb {

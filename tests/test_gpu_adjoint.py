@@ -249,6 +249,35 @@ def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
         assert np.array_equal(grad, eager[1])
 
 
+def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
+    """The backward pass recomputes segment k - 1 on a second stream, into a
+    second workspace, while segment k is reversed (vdwlb_adjoint_recompute /
+    vdwlb_adjoint_reverse); the gradient equals the one-stream loop of
+    vdwlb_adjoint_segment bit for bit, with unequal segments (20 x 4 + 10),
+    with and without graphs, over repeated backward passes."""
+    adjoint, _, _ = gpu
+    P = mixture(2)
+    k_hat = P["kappa"] / 0.1
+    nx, ny, nsteps = 48, 40, 90
+    rng = np.random.default_rng(8)
+    rho0 = 2.625 * (1 + 0.01 * rng.uniform(-1, 1, (2, ny, nx)))
+    tg = torch.as_tensor(rho0[0].mean() * (1 + 0.05 * np.sin(2 * np.pi * np.arange(nx) / nx))[None, :].repeat(ny, 0),
+                         device="cuda")
+    theta = adjoint.theta_from_params(P["kT"], P["a"], P["b"], 0.1)
+    spec = adjoint.Spec(nx, ny, 2, k_hat, nsteps, ckpt=20, tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"])
+    loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
+    r0 = torch.as_tensor(rho0, device="cuda")
+    monkeypatch.setenv("VDWLB_ADJ_SERIAL", "1")
+    serial = adjoint.run_and_grad(theta, r0, spec, loss_fn)
+    monkeypatch.delenv("VDWLB_ADJ_SERIAL")
+    runs = [adjoint.run_and_grad(theta, r0, spec, loss_fn) for _ in range(2)]
+    monkeypatch.setenv("VDWLB_NO_GRAPH", "1")
+    runs.append(adjoint.run_and_grad(theta, r0, spec, loss_fn))
+    for loss, grad in runs:
+        assert loss == serial[0]
+        assert np.array_equal(grad, serial[1])
+
+
 @pytest.mark.parametrize("tau", [1.0, 0.8])
 def test_row_schedules_equal_default(gpu, tau):
     """The recompute inside the backward pass runs the plan's sweep schedule
