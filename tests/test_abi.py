@@ -84,6 +84,10 @@ def test_null_arguments():
     assert V.lib().vdwlb_step(None, None, None, 1, None, None) == V.E_INVALID_ARG
     assert V.lib().vdwlb_state_bytes(None) == 0
     assert V.lib().vdwlb_plan_destroy(None) == V.OK
+    assert V.lib().vdwlb_adjoint_segment(None, None, 1, None, None, None, None) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_adjoint_recompute(None, None, 1, None, None) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_adjoint_reverse(None, 1, None, None, None, None) == V.E_INVALID_ARG
+    assert V.lib().vdwlb_adjoint_workspace_bytes(None, 100) == 0
 
 
 def test_dimension_rules():

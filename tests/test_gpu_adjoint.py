@@ -249,6 +249,42 @@ def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
         assert np.array_equal(grad, eager[1])
 
 
+def test_adjoint_entry_points_validate(gpu):
+    """The segment, recompute and reverse entry points reject a step count
+    below 1 and misaligned buffers, and report FP32, D1Q3 and C > 2 plans
+    as unsupported, all before any launch."""
+    adjoint, lattice, V = gpu
+    lib = V.lib()
+    a = np.array([[A11, 0.9 * A11], [0.9 * A11, A11]])
+    plan = lattice.Plan(16, 16, 0.45, a, np.array([B1, B1]), 0.1 * np.ones((2, 2)))
+    n = plan.state_bytes // 8
+    ws_bytes = int(lib.vdwlb_adjoint_workspace_bytes(plan.handle, 4))
+    f = torch.zeros(n + 2, dtype=torch.float64, device="cuda")
+    fb = torch.zeros(n + 2, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(ws_bytes // 8 + 2, dtype=torch.float64, device="cuda")
+    pbar = torch.zeros(int(lib.vdwlb_adjoint_param_count(plan.handle)), dtype=torch.float64, device="cuda")
+    h = plan.handle
+    F, FB, W, PB = f.data_ptr(), fb.data_ptr(), ws.data_ptr(), pbar.data_ptr()
+    assert lib.vdwlb_adjoint_recompute(h, F, 0, W, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_reverse(h, 0, FB, W, PB, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_segment(h, F, 0, FB, W, PB, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_recompute(h, F + 8, 4, W, None) == V.E_INVALID_ARG  # 16-byte elements
+    assert lib.vdwlb_adjoint_recompute(h, F, 4, W + 8, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_reverse(h, 4, FB + 8, W, PB, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_reverse(h, 4, FB, W, None, None) == V.E_INVALID_ARG
+    for kw in (dict(dtype="f32"), dict(dim=1)):
+        other = lattice.Plan(16, 16 if kw.get("dim", 2) == 2 else 1, 0.45, a, np.array([B1, B1]),
+                             0.1 * np.ones((2, 2)), **kw)
+        assert lib.vdwlb_adjoint_recompute(other.handle, F, 4, W, None) == V.E_UNSUPPORTED
+        assert lib.vdwlb_adjoint_reverse(other.handle, 4, FB, W, PB, None) == V.E_UNSUPPORTED
+    a3 = np.full((3, 3), 0.9 * A11)
+    np.fill_diagonal(a3, A11)
+    three = lattice.Plan(16, 16, 0.45, a3, np.full(3, B1), 0.1 * np.ones((3, 3)))
+    assert lib.vdwlb_adjoint_segment(three.handle, F, 4, FB, W, PB, None) == V.E_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert lib.vdwlb_sync_status(h, None) == V.OK
+
+
 def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
     """The backward pass recomputes segment k - 1 on a second stream, into a
     second workspace, while segment k is reversed (vdwlb_adjoint_recompute /
