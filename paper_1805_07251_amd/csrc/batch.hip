@@ -3,10 +3,12 @@
 //
 // Workgroups take instances from a queue ordered largest first (longest
 // processing time first) and run every step of an instance before taking the
-// next one, so an instance's two population buffers stay in L2/MALL for its
-// whole run instead of streaming through HBM each step.  Each step walks the
-// instance in full-height strips of TX columns whose rows wrap inside LDS
-// (strip_step), with exactly the per-site arithmetic of the plain sweep.
+// next one: one queue pop per instance and no grid-wide synchronisation
+// between steps.  (With one workgroup per CU the buffers of the instances in
+// flight on an XCD exceed its L2, so each step's populations still come from
+// beyond L2, as in the plain sweep.)  Each step walks the instance in
+// full-height strips of TX columns whose rows wrap inside LDS (strip_step),
+// with exactly the per-site arithmetic of the plain sweep.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
