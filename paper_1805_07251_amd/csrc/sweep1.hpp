@@ -59,23 +59,25 @@ __device__ __forceinline__ T grad3(T gm, T gp) {
 }
 
 // Collision of one component at one site (in place on p).  Opposite
-// velocities share the even part of feq and F.
+// velocities share the even part of feq and F; the rest population comes
+// last, from the mass balance f'_0 = rho - f'_+ - f'_- (as in the D2Q9
+// collision: its direct form would drop u^2 terms below the rounding step
+// with a fixed sign).
 template <typename T, bool TAU1>
 __device__ __forceinline__ void collide1(T (&p)[Q1], T rho, T ri, T jx, T gx, T lap, T omega, T cG, T cL) {
     const T ux = jx * ri;
     const T S = T(2) * gx * ux + cG * gx * gx * ri + cL * lap;
     const T base = T(1) - T(1.5) * ux * ux;
     const T r1 = T(1.0 / 6.0) * rho;
-    const T f0 = T(2.0 / 3.0) * rho * base;
     const T ev = r1 * (base + T(4.5) * ux * ux), od = T(3) * r1 * ux;
     const T fe = T(0.5) * S, fo = T(0.5) * gx;
     auto out = [&](int i, T feq, T force) {
         if constexpr (TAU1) p[i] = feq + force;
         else p[i] = p[i] + omega * (feq - p[i]) + force;
     };
-    out(0, f0, -S);
     out(1, ev + od, fe + fo);
     out(2, ev - od, fe - fo);
+    p[0] = rho - (p[1] + p[2]);
 }
 
 // Friction, collision and store of one site (x components only: in 1-D the
