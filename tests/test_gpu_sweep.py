@@ -67,7 +67,7 @@ def test_spinodal_small_f32_1000_steps(gpu, orc):
     rho_ref = ref.moments()[0]
     lat = gpu_run(gpu, w, 1000, dtype="f32")
     rho = lat.moments(want_mu=False, want_p=False)[0]
-    assert rel_err(np_(rho), rho_ref) <= 1e-4
+    assert rel_err(np_(rho), rho_ref) <= 1e-5  # measured 8.6e-6
 
 
 N_SCHED = 40
@@ -370,10 +370,11 @@ def _radial_peak(r):
 def test_f32_full_runs_against_f64(gpu, name, steps):
     """The FP32 benchmark workloads over their full runs (2048^2 C = 2, 10,000
     steps; 1024^2 C = 4, 5,000 steps), where no oracle window reaches: every
-    component's mass stays within 1e-5 of its start (the FP64 run within
-    1e-11), and the structure factor of every component peaks at the same
-    wavenumber as in the FP64 run (itself checked against the oracle) with a
-    height within 5 % (measured: 0.2 %)."""
+    component's mass stays within 1e-5 of its start (measured 1.9e-6 and
+    1.2e-6; the FP64 runs within 1e-13, measured 4e-15 and 1e-15), and the
+    structure factor of every component peaks at the same wavenumber as in the
+    FP64 run (itself checked against the oracle) with a height within 5 %
+    (measured: 0.08 %)."""
     mk = getattr(I, name)
     out = {}
     for dt in ("f64", "f32"):
@@ -387,7 +388,7 @@ def test_f32_full_runs_against_f64(gpu, name, steps):
         rho = np_(lat.moments(False, False)[0]).astype(np.float64)
         out[dt] = rho
         drift = np.abs(rho.sum(axis=(1, 2)) - m0) / m0
-        assert drift.max() <= (1e-11 if dt == "f64" else 1e-5), (dt, drift)
+        assert drift.max() <= (1e-13 if dt == "f64" else 1e-5), (dt, drift)
     for c in range(out["f64"].shape[0]):
         k64, h64 = _radial_peak(out["f64"][c])
         k32, h32 = _radial_peak(out["f32"][c])
