@@ -48,8 +48,10 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and V._lib is not None:
-            V.lib().vdwlb_batch_destroy(h)
+        # at interpreter exit the module globals may already be gone
+        lib = getattr(V, "_lib", None) if V is not None else None
+        if h is not None and lib is not None:
+            lib.vdwlb_batch_destroy(h)
             self.handle = None
 
     def set_launch(self, threads=256, blocks=0):

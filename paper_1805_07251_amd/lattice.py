@@ -55,8 +55,10 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and V._lib is not None:
-            V.lib().vdwlb_plan_destroy(h)
+        # at interpreter exit the module globals may already be gone
+        lib = getattr(V, "_lib", None) if V is not None else None
+        if h is not None and lib is not None:
+            lib.vdwlb_plan_destroy(h)
             self.handle = None
 
     @property

@@ -65,7 +65,7 @@ def test_line_f32(gpu, orc):
     w = I.line_spinodal(1, L=300, dtype="f32")
     ref, _ = oracle_run(orc, w, 500, dim=1)
     lat = gpu_line(lattice, w, 500)
-    assert rel_err(np_(lat.moments(want_mu=False, want_p=False)[0]), ref.moments()[0]) <= 1e-4
+    assert rel_err(np_(lat.moments(want_mu=False, want_p=False)[0]), ref.moments()[0]) <= 1e-5  # measured 4.3e-6
 
 
 @pytest.mark.parametrize("sched", range(4))
