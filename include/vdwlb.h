@@ -367,8 +367,12 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t
  * the two, by stream or event); it replaces fbar_io and adds to pbar_accum
  * exactly as vdwlb_adjoint_segment does, which is the recompute followed by
  * the reverse sweep on one stream.  A workspace must not be recomputed into
- * while a reverse sweep that reads it may still run.  Asynchronous on
- * stream; arguments and errors as for vdwlb_adjoint_segment. */
+ * while a reverse sweep that reads it may still run.  Each half is replayed
+ * from a hipGraph captured on first use and bound to its step count and
+ * buffers (the workspace; for the reverse sweep also fbar_io and pbar_accum);
+ * a plan keeps up to six such graphs, and makes the device idle before it
+ * drops the oldest.  Asynchronous on stream; arguments and errors as for
+ * vdwlb_adjoint_segment. */
 vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* workspace,
                                      void* stream);
 vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* plan, int32_t nsteps, void* fbar_io, void* workspace,
