@@ -100,6 +100,22 @@ def test_short_lines(gpu, orc, nx):
     np.testing.assert_allclose(np_(lat.state_sites()), ref.f, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_uniform_line_stays_uniform(gpu, dtype):
+    """A uniform state (two components) stays bitwise uniform over 40 steps
+    and keeps its densities to round-off (a few units in the last place per
+    step at most)."""
+    _, lattice = gpu
+    w = I.line_spinodal(0, L=777, dtype=dtype)
+    w.rho = np.ones_like(w.rho) * np.array([2.1, 3.0])[:, None, None]
+    lat = gpu_line(lattice, w, 40)
+    f = np_(lat.state_sites())
+    assert np.all(f == f[..., :1])
+    rho = np_(lat.moments(want_mu=False, want_p=False)[0]).astype(np.float64)
+    assert np.all(rho == rho[..., :1])
+    np.testing.assert_allclose(rho[:, 0, 0], [2.1, 3.0], rtol=1e-13 if dtype == "f64" else 1e-5)
+
+
 @pytest.mark.parametrize("C", [1, 3, 4])
 def test_component_counts(gpu, orc, C):
     _, lattice = gpu
