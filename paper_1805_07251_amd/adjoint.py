@@ -124,6 +124,19 @@ class VdwLBFunction(torch.autograd.Function):
         return torch.as_tensor(grad, dtype=ctx.theta_dtype, device=ctx.theta_device), None, None
 
 
+_AUX_STREAMS = {}
+
+
+def _aux_stream(dev):
+    """The second stream of the backward pass on device dev (default priority),
+    created once per device."""
+    d = torch.device(dev)
+    key = d.index if d.index is not None else torch.cuda.current_device()
+    if key not in _AUX_STREAMS:
+        _AUX_STREAMS[key] = torch.cuda.Stream(device=key)
+    return _AUX_STREAMS[key]
+
+
 def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev):
     """Reverse the segments from the last to the first with the forward
     recompute of segment k - 1 on a second stream, into a second workspace,
@@ -132,7 +145,7 @@ def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev):
     loop, so the results are the same bit for bit."""
     lib = V.lib()
     main = torch.cuda.current_stream(dev)
-    aux = torch.cuda.Stream(device=dev)
+    aux = _aux_stream(dev)
     ws = [torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev) for _ in range(2)]
     aux.wait_stream(main)  # checkpoints and workspaces are ready
     freed = [None, None]  # per workspace: the end of the last reverse sweep that reads it
