@@ -583,6 +583,8 @@ def _inputs():
 
 # The legs besides the headline, by name (each takes the parsed arguments).
 LEGS = {
+    # the 64^2 correctness case: L2-resident, so a latency figure, not a roofline one
+    "spinodal_64_f64": lambda a: sweep_line(_inputs().spinodal_small(a.seed), "f64", 1000, a.warmup),
     "spinodal_2048_f32": lambda a: sweep_line(_inputs().spinodal_large(a.seed, dtype="f32"), "f32", a.steps,
                                               a.warmup),
     "mixture4_1024_f32": lambda a: sweep_line(_inputs().mixture4(a.seed), "f32", 5000, a.warmup),
@@ -653,7 +655,7 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["headline_protocol"] = protocol_leg(w, "f64", head["schedule"])
-        for n in ("spinodal_2048_f32", "mixture4_1024_f32"):
+        for n in ("spinodal_64_f64", "spinodal_2048_f32", "mixture4_1024_f32"):
             extra[n] = LEGS[n](args)
         extra["copy_kernel_gbs"] = copy_gbs()
         for n in ("batched", "d1q3_line_16M_f64", "batched_d1q3", "adjoint"):
