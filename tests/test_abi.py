@@ -77,6 +77,24 @@ def test_plan_create_validates_before_touching_the_device(bad):
     assert h.value is None
 
 
+def test_plan_size_limits_checked_on_the_host():
+    """More than 2^28 sites, or a velocity plane of 2^32 bytes or more (the
+    kernels address a plane with 32-bit byte offsets), is refused before any
+    device call."""
+    import ctypes
+
+    d, keep = _desc(nx=20000, ny=20000)  # 4e8 sites
+    h = ctypes.c_void_p(1)
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
+    a4 = np.full((4, 4), 0.1) + 0.1 * np.eye(4)
+    b4 = np.full(4, 0.1)
+    k4 = np.full((4, 4), 0.05) + 0.05 * np.eye(4)
+    p = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d = V.Desc(2, 12000, 12000, 4, V.F64, V.FORCE_LOG, 0.4, 1.0, 0.25, p(a4), p(b4), p(k4), None)  # 4.6e9 B plane
+    assert V.lib().vdwlb_plan_create(ctypes.byref(d), ctypes.byref(h)) == V.E_INVALID_ARG
+    assert h.value is None
+
+
 def test_null_arguments():
     import ctypes
 
