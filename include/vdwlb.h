@@ -62,7 +62,8 @@ enum {
     VDWLB_E_INVALID_ARG = 1, /* a NULL pointer, a bad size or a parameter outside its domain */
     VDWLB_E_UNSUPPORTED = 2, /* a valid request the library does not implement (dim, C, dtype) */
     VDWLB_E_DEVICE = 3,      /* a HIP runtime error; vdwlb_last_device_error() has its text */
-    VDWLB_E_UNPHYSICAL = 4   /* the sticky device flag: rho^c <= 0, eta >= 1 or a non-finite value */
+    VDWLB_E_UNPHYSICAL = 4,  /* the sticky device flag: rho^c <= 0, eta >= 1 or a non-finite value */
+    VDWLB_E_CAPACITY = 5     /* the request needs more than a fixed capacity (the no-allocation scratch) */
 };
 
 enum { VDWLB_F64 = 0, VDWLB_F32 = 1 };             /* storage and arithmetic precision */
@@ -354,6 +355,28 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* plan, const void* rho_bar, const 
  * stream. */
 vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
                                    void* workspace, double* pbar_accum, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * vdwlb_adjoint_segment with its workspace taken from a fixed device array of
+ * VDWLB_ADJOINT_SCRATCH_BYTES bytes that the library's code object holds on
+ * every device it runs on until the process ends.  The call itself allocates
+ * nothing: no hipMalloc / hipFree, no graph instantiation (its kernels are
+ * launched one by one on stream, so a caller may capture them), only kernel
+ * launches and device-to-device copies.
+ *   Arguments, results and errors are those of vdwlb_adjoint_segment without
+ *   the workspace argument; the results are the same bit for bit.
+ *   VDWLB_E_CAPACITY when vdwlb_adjoint_workspace_bytes(plan, nsteps) exceeds
+ *   VDWLB_ADJOINT_SCRATCH_BYTES (nothing is enqueued): use shorter segments.
+ *   The device address of the array is looked up once per device, on the
+ *   first call that uses that device (the plan's device).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (no part of it needs to start at zero): calls that can
+ * overlap on one device, on any streams or plans, race and must be ordered
+ * by the caller.  Asynchronous on stream. */
+#define VDWLB_ADJOINT_SCRATCH_BYTES ((size_t)64 << 20)
+vdwlb_status vdwlb_adjoint_segment_noalloc(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
+                                           double* pbar_accum, void* stream);
 
 /* The two halves of vdwlb_adjoint_segment, for callers that overlap the
  * forward recompute of one segment with the reverse sweep of the next one on

@@ -21,12 +21,20 @@
 //     pulled-population cotangent pb_i = (1 - omega) fb'_i + rhob + jb.v_i
 //     is un-streamed: fb_i(x - v_i) = pb_i(x).
 #include <cstdio>
-#include <vector>
-
 #include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "../../include/vdwlb.h"
 #include "launch.hpp"
+
+// Workspace of vdwlb_adjoint_segment_noalloc: a fixed array in this code
+// object's static device storage, one copy per device, held until the process
+// ends.  In host code its name stands for a host-side shadow, not a device
+// address: host code takes the device address of each device's copy from
+// hipGetSymbolAddress (scratch_address below) and passes only that to kernels
+// and copies.
+static __device__ __align__(256) unsigned char scratch[VDWLB_ADJOINT_SCRATCH_BYTES];
 
 namespace vdwlb {
 namespace adj {
@@ -752,6 +760,33 @@ vdwlb_status run_part(vdwlb_plan& p, const AdjointGraph& key, hipStream_t s, Enq
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, what);
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller's current device is restored).
+hipError_t scratch_address(int device, void** out) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void* ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch));
+        if (cur >= 0 && cur != device) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+
 vdwlb_status check_adjoint(const vdwlb_plan* p, int32_t nsteps, const void* workspace) {
     if (!p || !workspace || nsteps < 1) return VDWLB_E_INVALID_ARG;
     if (!state_aligned(*p, workspace)) return VDWLB_E_INVALID_ARG;
@@ -844,6 +879,29 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
     st = vdwlb_adjoint_recompute(p, f_ckpt, nsteps, workspace, stream);
     if (st != VDWLB_OK) return st;
     return vdwlb_adjoint_reverse(p, nsteps, fbar_io, workspace, pbar_accum, stream);
+}
+
+vdwlb_status vdwlb_adjoint_segment_noalloc(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io,
+                                           double* pbar_accum, void* stream) {
+    if (!p || nsteps < 1) return VDWLB_E_INVALID_ARG;
+    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+    if (!f_ckpt || !fbar_io || !pbar_accum || !state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io))
+        return VDWLB_E_INVALID_ARG;
+    if (vdwlb_adjoint_workspace_bytes(p, nsteps) > VDWLB_ADJOINT_SCRATCH_BYTES) return VDWLB_E_CAPACITY;
+    void* ws = nullptr;
+    hipError_t e = scratch_address(p->device, &ws);
+    if (e != hipSuccess) return set_device_error(e, "adjoint scratch address");
+    const vdwlb_status st = check_adjoint(p, nsteps, ws);
+    if (st != VDWLB_OK) return st;
+    // the kernel sequence of vdwlb_adjoint_recompute and vdwlb_adjoint_reverse,
+    // launched one by one instead of replayed from a graph
+    const Layout L = layout(*p, nsteps);
+    hipStream_t s = (hipStream_t)stream;
+    double* w = (double*)ws;
+    e = hipMemcpyAsync(w + L.f0, f_ckpt, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = enqueue_recompute(*p, L, w, nsteps, s);
+    if (e == hipSuccess) e = enqueue_reverse(*p, L, w, nsteps, (double*)fbar_io, pbar_accum, s, adjoint_fused());
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint segment (no allocation)");
 }
 
 }  // extern "C"

@@ -112,6 +112,7 @@ const char* vdwlb_strerror(vdwlb_status s) {
         case VDWLB_E_UNSUPPORTED: return "unsupported configuration";
         case VDWLB_E_DEVICE: return "HIP device error";
         case VDWLB_E_UNPHYSICAL: return "unphysical state (rho <= 0, eta >= 1 or non-finite value)";
+        case VDWLB_E_CAPACITY: return "request exceeds the fixed capacity of the no-allocation scratch";
         default: return "unknown status";
     }
 }

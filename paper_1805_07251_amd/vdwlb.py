@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvdwlb.so")
 
-OK, E_INVALID_ARG, E_UNSUPPORTED, E_DEVICE, E_UNPHYSICAL = 0, 1, 2, 3, 4
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_DEVICE, E_UNPHYSICAL, E_CAPACITY = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 FORCE_LOG, FORCE_NID = 0, 1
 
@@ -72,6 +72,7 @@ _SIGS = {
     "vdwlb_adjoint_segment": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "vdwlb_adjoint_recompute": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
     "vdwlb_adjoint_reverse": (ctypes.c_int32, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+    "vdwlb_adjoint_segment_noalloc": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     "vdwlb_pressure_tensor": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "vdwlb_phase_points": (ctypes.c_int32, [ctypes.c_double, _c_double_p, _c_double_p, ctypes.c_int32, _VP, _VP,
                                             ctypes.c_double, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
