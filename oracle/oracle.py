@@ -33,9 +33,9 @@ def build(force: bool = False) -> str:
     objs = []
     for tag, extra in (("re", []), ("cx", ["-DORC_COMPLEX"])):
         obj = os.path.join(_HERE, f"_orc_{tag}.o")
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-Wall", "-c", _SRC, "-o", obj] + extra)
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-Wall", "-fopenmp", "-c", _SRC, "-o", obj] + extra)
         objs.append(obj)
-    subprocess.check_call(["gcc", "-shared", "-o", tmp] + objs + ["-lm"])
+    subprocess.check_call(["gcc", "-shared", "-fopenmp", "-o", tmp] + objs + ["-lm"])
     os.replace(tmp, _LIB)
     for o in objs:
         os.remove(o)
@@ -66,6 +66,15 @@ def _load():
             for name in ("orc_step", "orc_run", "orc_equilibrium_state", "orc_moments"):
                 getattr(_lib, name + sfx).restype = ctypes.c_int
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads for the oracle's per-site loops on lattices of at least 16,384
+    sites (n <= 0: the OpenMP default, all host cores); returns the count in
+    effect.  Results do not depend on it."""
+    L = _load()
+    L.orc_set_threads.restype = ctypes.c_int
+    return int(L.orc_set_threads(ctypes.c_int(n)))
 
 
 def _ptr(a):

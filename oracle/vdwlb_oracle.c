@@ -45,6 +45,11 @@
  * Scalar type: built twice, once with real_t = double and once with
  * real_t = double complex (-DORC_COMPLEX, symbols suffixed _cx), so the same
  * arithmetic gives complex-step derivatives (Squire & Trapp 1998).
+ *
+ * Threads: the per-site loops of large lattices are split over OpenMP threads
+ * (orc_set_threads).  Every site's arithmetic is the same whatever thread
+ * runs it and no value is summed across sites, so results do not depend on
+ * the thread count (checked bit for bit by the tests).
  */
 #include <stddef.h>
 #include <stdlib.h>
@@ -62,6 +67,12 @@ typedef double real_t;
 #endif
 #include <tgmath.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Lattices with fewer sites run their loops on one thread. */
+#define ORC_PAR_MIN 16384
 
 #define ORC_OK 0
 #define ORC_INVALID 1
@@ -113,6 +124,20 @@ static lattice_t lattice_of(int dim) {
     }
     return L;
 }
+
+#ifndef ORC_COMPLEX
+/* Threads for the per-site loops (n <= 0: the OpenMP default); returns the
+ * count now in effect (1 without OpenMP). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+#endif
 
 static int wrap(int i, int n) {
     int r = i % n;
@@ -215,15 +240,16 @@ static void solve_small(int n, real_t* A, real_t* r, real_t* x) {
 static int chem_pot(const orc_config* k, const lattice_t* L, const real_t* prm, const real_t* rho, real_t* mu) {
     const int C = k->C, nx = k->nx, ny = k->ny;
     const size_t N = (size_t)nx * ny;
-    int status = ORC_OK;
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad) if (N >= ORC_PAR_MIN)
     for (size_t s = 0; s < N; ++s) {
         real_t eta = 0, rt = 0;
         for (int c = 0; c < C; ++c) {
             eta += PRM_B(prm, C, c) * rho[c * N + s];
             rt += rho[c * N + s];
-            if (!(RE(rho[c * N + s]) > 0.0) || is_bad(rho[c * N + s])) status = ORC_UNPHYSICAL;
+            if (!(RE(rho[c * N + s]) > 0.0) || is_bad(rho[c * N + s])) bad = 1;
         }
-        if (!(RE(eta) < 1.0)) status = ORC_UNPHYSICAL;
+        if (!(RE(eta) < 1.0)) bad = 1;
         for (int c = 0; c < C; ++c) {
             real_t m = PRM_KT(prm) * (log(rho[c * N + s] / (1.0 - eta)) + PRM_B(prm, C, c) * rt / (1.0 - eta));
             for (int d = 0; d < C; ++d)
@@ -231,10 +257,10 @@ static int chem_pot(const orc_config* k, const lattice_t* L, const real_t* prm, 
                     m += 2.0 * psi(L, k->dim, PRM_A(prm, C, c, d), PRM_K(prm, C, c, d), q) *
                          rho[d * N + nbr(L, nx, ny, s, q)];
             mu[c * N + s] = m;
-            if (is_bad(m)) status = ORC_UNPHYSICAL;
+            if (is_bad(m)) bad = 1;
         }
     }
-    return status;
+    return bad ? ORC_UNPHYSICAL : ORC_OK;
 }
 
 /* Moments of the streamed populations: rho^c = sum_i f_i^c,
@@ -242,6 +268,7 @@ static int chem_pot(const orc_config* k, const lattice_t* L, const real_t* prm, 
 static void moments_of(const orc_config* k, const lattice_t* L, const real_t* p, real_t* rho, real_t* jx, real_t* jy) {
     const size_t N = (size_t)k->nx * k->ny;
     for (int c = 0; c < k->C; ++c)
+#pragma omp parallel for if (N >= ORC_PAR_MIN)
         for (size_t s = 0; s < N; ++s) {
             real_t r = 0, x = 0, y = 0;
             for (int i = 0; i < L->Q; ++i) {
@@ -262,6 +289,7 @@ static void stream_pull(const orc_config* k, const lattice_t* L, const real_t* f
     const size_t N = (size_t)nx * ny;
     for (int c = 0; c < k->C; ++c)
         for (int i = 0; i < L->Q; ++i)
+#pragma omp parallel for if (N >= ORC_PAR_MIN)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     size_t src = (size_t)wrap(y - L->vy[i], ny) * nx + (size_t)wrap(x - L->vx[i], nx);
@@ -300,10 +328,12 @@ int SFX(orc_step)(const orc_config* k, const real_t* prm, const double* lambda, 
      *    G = -rho grad(gamma mu) + theta grad(rho);
      *    nid (Eq. forceMuId): G = -rho grad(gamma mu - theta ln rho). */
     for (int c = 0; c < C; ++c)
+#pragma omp parallel for if (N >= ORC_PAR_MIN)
         for (size_t s = 0; s < N; ++s)
             phi[c * N + s] = (k->force == 1) ? gam * mu[c * N + s] - THETA_LB * log(rho[c * N + s])
                                              : gam * mu[c * N + s];
     for (int c = 0; c < C; ++c)
+#pragma omp parallel for if (N >= ORC_PAR_MIN)
         for (size_t s = 0; s < N; ++s) {
             real_t dpx, dpy;
             grad_at(&L, nx, ny, phi + c * N, s, &dpx, &dpy);
@@ -321,10 +351,13 @@ int SFX(orc_step)(const orc_config* k, const real_t* prm, const double* lambda, 
      *    uh^c = u^c + G^c/(2 rho^c), G^c including the friction itself:
      *    rho^c uh^c - (1/2) sum_c' W^{cc'} (uh^c' - uh^c) = j^c + G^{mu,c}/2,
      *    W^{cc'} = lambda^{cc'} rho^c rho^c' / (rho^c + rho^c'). */
+#pragma omp parallel if (N >= ORC_PAR_MIN)
+    {
     real_t* A = malloc(sizeof(real_t) * C * C);
     real_t* r = malloc(sizeof(real_t) * C);
     real_t* uh = malloc(sizeof(real_t) * C);
     real_t* W = malloc(sizeof(real_t) * C * C);
+#pragma omp for
     for (size_t s = 0; s < N; ++s) {
         for (int c = 0; c < C; ++c)
             for (int d = 0; d < C; ++d)
@@ -356,10 +389,13 @@ int SFX(orc_step)(const orc_config* k, const real_t* prm, const double* lambda, 
     free(r);
     free(uh);
     free(W);
+    }
 
     /* 6. forced BGK collision (Eqs. BGKcollisionOperator, feq, forcing
      *    moments with Psi of Eq. forceCorrectionsPsi). */
+    int bad = 0;
     for (int c = 0; c < C; ++c)
+#pragma omp parallel for reduction(| : bad) if (N >= ORC_PAR_MIN)
         for (size_t s = 0; s < N; ++s) {
             real_t rh = rho[c * N + s];
             real_t ux = jx[c * N + s] / rh, uy = jy[c * N + s] / rh;
@@ -385,9 +421,10 @@ int SFX(orc_step)(const orc_config* k, const real_t* prm, const double* lambda, 
                 }
                 real_t f0 = feq(&L, i, rh, ux, uy);
                 fout[idx] = p[idx] + (f0 - p[idx]) / tau + Fi;
-                if (is_bad(fout[idx])) status = ORC_UNPHYSICAL;
+                if (is_bad(fout[idx])) bad = 1;
             }
         }
+    if (bad) status = ORC_UNPHYSICAL;
 
     free(p);
     free(rho);

@@ -675,3 +675,30 @@ def test_pressure_tensor_bulk_of_converged_interface(orc):
     pm = T.pressure([rl], kT, p.a, p.b)
     assert abs(pxx[0, L // 2] - pm) < 1e-9 * abs(pm)
     assert abs(pxx[0, 0] - pm) < 1e-9 * abs(pm)
+
+
+# ---------------------------------------------------------------- threads
+def test_thread_count_does_not_change_results(orc):
+    """The per-site loops of lattices of 16,384 sites or more run on several
+    threads; each site's arithmetic is the same on any thread and nothing is
+    summed across sites, so 1 and 4 threads give the same state bit for bit
+    (real and complex builds, with C = 3 for the friction solve)."""
+    nx, ny = 160, 128
+    out = {}
+    try:
+        for nt in (1, 4):
+            assert orc.set_threads(nt) == nt
+            p = mix_params(orc, C=3)
+            lat = orc.Lattice(p, 2, nx, ny)
+            lat.init(noisy(np.random.default_rng(12), 3, ny, nx, mean=1.75, amp=0.05))
+            assert lat.run(3) == 0
+            lc = orc.Lattice(mix_params(orc), 2, nx, ny, complex_step=True)
+            lc.prm = lc.prm.astype(np.complex128)
+            lc.prm[0] += 1e-20j
+            lc.init(noisy(np.random.default_rng(13), 2, ny, nx, amp=0.05))
+            assert lc.run(2) == 0
+            out[nt] = (lat.f.copy(), lc.f.copy())
+    finally:
+        orc.set_threads(0)
+    assert np.array_equal(out[1][0], out[4][0])
+    assert np.array_equal(out[1][1], out[4][1])
