@@ -144,3 +144,30 @@ def test_full_batch_sampled(gpu):
         if st[k] == 0:
             assert np.array_equal(b.state(k).cpu().numpy(), plain_state(lattice, ws[k], 100)), k
     assert (st == 0).mean() > 0.9
+
+
+def test_full_size_instances_against_oracle(gpu, orc):
+    """The 1024-lattice workload in the benchmark's launch shape (1024-thread
+    workgroups), 200 steps: the smallest, a middle-sized and the largest
+    instance (L = 128 .. 1024, several strips each, the single-wrap path of
+    every production instance) against the oracle, element by element on the
+    densities within 1e-12 of the largest density, the FP64 bound used for
+    runs of hundreds of steps (round-off grows with the step count: measured
+    1.3e-13 at L = 128 after 200 steps, against 1e-13 after 30)."""
+    batch, _ = gpu
+    d = I.batch_draws(0)
+    ws = slabs(0, range(len(d.L)))
+    b = batch_run(batch, ws, 200, threads=1024)
+    st = b.status()
+    order = np.argsort(d.L, kind="stable")
+    mid = int(np.argmin(np.abs(np.asarray(d.L) - 577)))
+    picks = [int(order[0]), mid, int(order[-1])]
+    assert d.L[picks[0]] <= 140 and d.L[picks[2]] >= 1000
+    rho = b.densities()
+    for k in picks:
+        assert st[k] == 0, k
+        ref, ost = oracle_run(orc, ws[k], 200)
+        assert ost == 0
+        err = rel_err(rho[k].cpu().numpy(), ref.moments()[0])
+        print(f"batch instance {k}: L = {d.L[k]}, max rel density error {err:.2e}", flush=True)
+        assert err <= 1e-12, k
