@@ -492,28 +492,61 @@ def verification_leg(n=16, steps=50000):
     return out
 
 
-def cpu_baseline(w, steps=8, seed=0, legs=True):
-    """The CPU oracle on the same workload for a few steps (single thread),
-    and with `legs` bounded samples beside the other GPU legs: the first 32
-    lattices of the batched workload, complex-step gradient directions of the
-    adjoint case, and Appendix A points of the phase-diagram leg."""
-    from oracle import oracle as O
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
+
+def _oracle_sweep(O, w, steps, threads):
+    used = O.set_threads(threads)
     lat = O.Lattice(O.Params(w.kT, w.a, w.b, w.kappa, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam), 2, w.nx, w.ny)
     lat.init(w.rho)
     t0 = time.perf_counter()
     lat.run(steps)
     secs = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * w.C * steps / secs / 1e6, "unit": "MLUPS×C", "cores": used, "steps": steps,
+            "seconds": secs}
+
+
+def cpu_baseline(w, seed=0, legs=True, steps_all=16, steps_one=4):
+    """The CPU oracle on the same workload for a few steps, on all host cores
+    (OpenMP over sites; the value reported) and on one thread, with the host's
+    CPU model and core count; with `legs` bounded single-thread samples beside
+    the other GPU legs: the first 32 lattices of the batched workload,
+    complex-step gradient directions of the adjoint case, and Appendix A
+    points of the phase-diagram leg."""
+    from oracle import oracle as O
+
+    allc = _oracle_sweep(O, w, steps_all, 0)
+    one = _oracle_sweep(O, w, steps_one, 1)
     out = {
-        "value": w.nx * w.ny * w.C * steps / secs / 1e6,
+        "value": allc["value"],
         "unit": "MLUPS×C",
-        "cores": 1,
+        "cores": allc["cores"],
         "kind": "oracle",
-        "sample": f"{steps} steps of the same {w.nx}x{w.ny} C={w.C} FP64 workload, single-threaded C oracle",
-        "seconds": secs,
+        "sample": f"{steps_all} steps of the same {w.nx}x{w.ny} C={w.C} FP64 workload, C oracle with its per-site "
+                  f"loops on {allc['cores']} OpenMP threads",
+        "seconds": allc["seconds"],
+        "single_thread": one,
+        "host": host_cpu(),
     }
     if legs:
+        O.set_threads(1)
         out["legs"] = cpu_legs(O, seed)
+        O.set_threads(0)
     return out
 
 

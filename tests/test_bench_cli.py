@@ -36,3 +36,16 @@ def test_traffic_follows_the_profiled_sources(monkeypatch):
     assert bench.traffic_from_profiles(7) is None
     monkeypatch.setattr(bench, "sweep_source_hash", lambda: "0" * 64)
     assert bench.traffic_from_profiles(25) is None
+
+
+def test_cpu_baseline_reports_cores_and_host():
+    """The oracle baseline carries the all-cores figure (threads actually
+    used), the one-thread figure and the host's CPU model and core count."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1805_07251_amd import inputs as I
+
+    cb = bench.cpu_baseline(I.spinodal_small(0, n=32), legs=False, steps_all=2, steps_one=1)
+    assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS×C" and cb["value"] > 0
+    assert cb["cores"] >= 1 and cb["single_thread"]["cores"] == 1 and cb["single_thread"]["value"] > 0
+    assert cb["host"]["nproc"] >= 1 and isinstance(cb["host"]["model"], str)
