@@ -186,8 +186,11 @@ vdwlb_status vdwlb_set_schedule(vdwlb_plan* plan, int32_t k);
 
 /* Time every schedule on this plan's lattice (reads fA, overwrites fB),
  * re-time the four fastest with more launches, keep the fastest and report it
- * in *chosen (may be NULL).  Synchronous.  fA may hold any state: the error
- * flag read by vdwlb_sync_status is left as it was before the call. */
+ * in *chosen (may be NULL).  The timed steps alternate between fB (first a
+ * copy of fA) and a temporary state buffer the call allocates and frees, as a
+ * run alternates between its two buffers.  Synchronous.  fA may hold any
+ * state: the error flag read by vdwlb_sync_status is left as it was before
+ * the call. */
 vdwlb_status vdwlb_autotune(vdwlb_plan* plan, const void* fA, void* fB, void* stream, int32_t* chosen);
 
 /* Liquid-gas coexistence of one van der Waals component (Eqs. tetcr, rhocr

@@ -228,13 +228,31 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     const int64_t sites = (int64_t)p->nx * p->ny;
     const int reps = sites >= (1 << 20) ? 10 : 50;
     const int keep_s = p->sched, keep_m = p->map_mode;
+    // Runs alternate between two state buffers, so the timed launches do too:
+    // between fB (first a copy of fA) and a temporary buffer.  Reading one
+    // input again and again would time lattices of up to half the 256 MB
+    // MALL from the cache, not at the rate of a run.  Without the temporary
+    // buffer (allocation failed) every launch reads fA.
+    const size_t bytes = vdwlb_state_bytes(p);
+    void* tmp = nullptr;
+    if (hipMalloc(&tmp, bytes) != hipSuccess) {
+        tmp = nullptr;
+        (void)hipGetLastError();
+    }
+    int parity = 0;
+    auto launch = [&]() -> hipError_t {
+        if (!tmp) return launch_sweep(*p, fA, fB, s);
+        const bool odd = (parity++ & 1) != 0;
+        return odd ? launch_sweep(*p, tmp, fB, s) : launch_sweep(*p, fB, tmp, s);
+    };
+    hipError_t e = tmp ? hipMemcpyAsync(fB, fA, bytes, hipMemcpyDeviceToDevice, s) : hipSuccess;
     // average launch time of public schedule k over n launches (after 3 warm-up launches)
     auto time_k = [&](int k, int n, float& ms) -> hipError_t {
         apply_public_schedule(*p, k);
         hipError_t e = hipSuccess;
-        for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch_sweep(*p, fA, fB, s);
+        for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch();
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; r < n && e == hipSuccess; ++r) e = launch_sweep(*p, fA, fB, s);
+        for (int r = 0; r < n && e == hipSuccess; ++r) e = launch();
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -245,7 +263,6 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
     // each in alternation, with four times the launches (single short timings
     // of schedules within a few per cent of each other are noise)
     std::vector<std::pair<float, int>> t;
-    hipError_t e = hipSuccess;
     for (int k = 0; k < public_schedule_count(*p) && e == hipSuccess; ++k) {
         float ms = 0;
         e = time_k(k, reps, ms);
@@ -262,6 +279,10 @@ vdwlb_status vdwlb_autotune(vdwlb_plan* p, const void* fA, void* fB, void* strea
         }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemcpy(p->d_flag, &keep_flag, sizeof keep_flag, hipMemcpyHostToDevice);
+    if (tmp) {
+        if (e != hipSuccess) (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_graph(*p);
