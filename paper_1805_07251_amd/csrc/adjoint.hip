@@ -39,8 +39,9 @@ static __device__ __align__(256) unsigned char scratch[VDWLB_ADJOINT_SCRATCH_BYT
 namespace vdwlb {
 namespace adj {
 
-constexpr int TX = 32, TY = 8;  // tile of kernel A
-constexpr int BLK = 256;        // workgroup of kernels B, C and the reduction
+constexpr int TX = 32, TY = 8;  // tile of the reverse-sweep kernels (A, B, fused)
+constexpr int BLK = 256;        // workgroup of the per-site kernels (C, moments adjoint, reduction)
+static_assert(TX * TY == BLK, "a tile is one workgroup of BLK threads");
 
 // number of parameters in the cotangent vector:
 // kT, a^{cd} (c <= d), b^c, kappa^{cd} (c <= d)
@@ -50,6 +51,9 @@ __host__ __device__ constexpr int pair_index(int C, int c, int d) {
     return (c <= d) ? c * C - c * (c - 1) / 2 + (d - c) : d * C - d * (d - 1) / 2 + (c - d);
 }
 
+// Per-step fields of the reverse sweep.  av, bv, lb, rhob_loc and jb exist
+// twice, by step parity: the fused kernel of step t reads step t + 1's values
+// around its tile while it writes step t's.
 struct Fields {
     const double* rho;  // [C][N] moments of the forward step
     const double* mom;  // [C][2][N]
@@ -62,262 +66,68 @@ struct Fields {
     double* lb_tot;     // [C][N]
 };
 
-__device__ __forceinline__ int wrapg(int v, int n) {
-    int r = v % n;
-    return r < 0 ? r + n : r;
-}
-
-// Kernel A: collision, friction and force adjoint at each site.
-template <int C>
-__global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn, Geometry g, Coeffs<C> k,
-                                                  Fields F) {
-    constexpr int EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2, NT = TX * TY;
-    __shared__ double s_rho[C][EY * EX];
-    __shared__ double s_phi[C][MY * MX];
-    const int N = g.nx * g.ny;
-    const int tiles_x = (g.nx + TX - 1) / TX;
-    const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
-    for (int e = threadIdx.x; e < EX * EY; e += NT) {
-        const int ey = e / EX, ex = e - ey * EX;
-        const int s = wrapg(y0 - 2 + ey, g.ny) * g.nx + wrapg(x0 - 2 + ex, g.nx);
-#pragma unroll
-        for (int c = 0; c < C; ++c) s_rho[c][e] = F.rho[(int64_t)c * N + s];
+// Periodic wrap of an index v that lies within a few sites of [0, n): by one
+// compare and select, or by a remainder when the geometry is flagged general
+// (extents too small for every index of a tile and its rings to lie within
+// one period of [0, n)).
+__device__ __forceinline__ int wrapg(int v, int n, int general) {
+    if (general) {
+        const int r = v % n;
+        return r < 0 ? r + n : r;
     }
-    __syncthreads();
-    for (int m = threadIdx.x; m < MX * MY; m += NT) {
-        const int my = m / MX, mx = m - my * MX;
-        double r[C], l[C], ph[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
-            l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
-        }
-        potential<double, C>(r, l, k, ph);
-#pragma unroll
-        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= g.nx || y >= g.ny) return;
-    const int s = y * g.nx + x;
-    const double omega = k.omega, cG = k.cG, cL = k.cL;
-
-    double rho[C], jx[C], jy[C], g0x[C], g0y[C], dpx[C], dpy[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        rho[c] = F.rho[(int64_t)c * N + s];
-        jx[c] = F.mom[(int64_t)(2 * c) * N + s];
-        jy[c] = F.mom[(int64_t)(2 * c + 1) * N + s];
-        double rx, ry;
-        grad9s<double, MX>(s_phi[c], lx + 1, ly + 1, dpx[c], dpy[c]);
-        grad9s<double, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
-        g0x[c] = -rho[c] * dpx[c];
-        g0y[c] = -rho[c] * dpy[c];
-        if (k.force == 0) {
-            g0x[c] += THETA * rx;
-            g0y[c] += THETA * ry;
-        }
-    }
-    // forward friction (C = 2 closed form)
-    double gx[C], gy[C];
-    double m = 0, K = 0, d0x = 0, d0y = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        gx[c] = g0x[c];
-        gy[c] = g0y[c];
-    }
-    if constexpr (C == 2) {
-        const double lam = k.lam(0, 1);
-        m = rho[0] * rho[1] / (rho[0] + rho[1]);
-        K = lam / (1.0 + 0.5 * lam);
-        d0x = (jx[1] + 0.5 * g0x[1]) / rho[1] - (jx[0] + 0.5 * g0x[0]) / rho[0];
-        d0y = (jy[1] + 0.5 * g0y[1]) / rho[1] - (jy[0] + 0.5 * g0y[0]) / rho[0];
-        gx[0] += K * m * d0x;
-        gx[1] -= K * m * d0x;
-        gy[0] += K * m * d0y;
-        gy[1] -= K * m * d0y;
-    }
-
-    // collision adjoint: h = omega [rho M0 + 3 j.M + Q(j)/rho] + 3 G.M
-    //                        + [2 G.B.j + cG Q(G)]/rho + cL L tr B
-    double rb[C], jbx[C], jby[C], gbx[C], gby[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        double M0 = 0, Mx = 0, My = 0, Mxx = 0, Myy = 0, Mxy = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-            const double fb = w * fbn[((int64_t)i * g.plane + s) * C + c];
-            const double vx = VX[i], vy = VY[i];
-            M0 += fb;
-            Mx += fb * vx;
-            My += fb * vy;
-            Mxx += fb * vx * vx;
-            Myy += fb * vy * vy;
-            Mxy += fb * vx * vy;
-        }
-        const double Bxx = 4.5 * Mxx - 1.5 * M0, Byy = 4.5 * Myy - 1.5 * M0, Bxy = 4.5 * Mxy;
-        const double r = rho[c], ri = 1.0 / r;
-        const double Jx = jx[c], Jy = jy[c], Gx = gx[c], Gy = gy[c];
-        const double Qj = Bxx * Jx * Jx + Byy * Jy * Jy + 2.0 * Bxy * Jx * Jy;
-        const double QG = Bxx * Gx * Gx + Byy * Gy * Gy + 2.0 * Bxy * Gx * Gy;
-        const double BJx = Bxx * Jx + Bxy * Jy, BJy = Bxy * Jx + Byy * Jy;
-        const double BGx = Bxx * Gx + Bxy * Gy, BGy = Bxy * Gx + Byy * Gy;
-        const double GBJ = Gx * BJx + Gy * BJy;
-        rb[c] = omega * (M0 - Qj * ri * ri) - (2.0 * GBJ + cG * QG) * ri * ri;
-        jbx[c] = omega * (3.0 * Mx + 2.0 * BJx * ri) + 2.0 * BGx * ri;
-        jby[c] = omega * (3.0 * My + 2.0 * BJy * ri) + 2.0 * BGy * ri;
-        gbx[c] = 3.0 * Mx + 2.0 * (BJx + cG * BGx) * ri;
-        gby[c] = 3.0 * My + 2.0 * (BJy + cG * BGy) * ri;
-        F.lb[(int64_t)c * N + s] = cL * (Bxx + Byy);
-    }
-    // friction adjoint: G = G0 + (+-) K m d0
-    double g0bx[C], g0by[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        g0bx[c] = gbx[c];
-        g0by[c] = gby[c];
-    }
-    if constexpr (C == 2) {
-        const double gfbx = gbx[0] - gbx[1], gfby = gby[0] - gby[1];
-        const double mb = K * (gfbx * d0x + gfby * d0y);
-        const double dbx = K * m * gfbx, dby = K * m * gfby;
-        const double s2 = (rho[0] + rho[1]) * (rho[0] + rho[1]);
-        rb[0] += mb * rho[1] * rho[1] / s2;
-        rb[1] += mb * rho[0] * rho[0] / s2;
-        // d0 = (j1 + G0_1/2)/rho1 - (j0 + G0_0/2)/rho0, per axis
-        const double i0 = 1.0 / rho[0], i1 = 1.0 / rho[1];
-        jbx[1] += dbx * i1;
-        jbx[0] -= dbx * i0;
-        jby[1] += dby * i1;
-        jby[0] -= dby * i0;
-        g0bx[1] += 0.5 * dbx * i1;
-        g0bx[0] -= 0.5 * dbx * i0;
-        g0by[1] += 0.5 * dby * i1;
-        g0by[0] -= 0.5 * dby * i0;
-        rb[1] -= (dbx * (jx[1] + 0.5 * g0x[1]) + dby * (jy[1] + 0.5 * g0y[1])) * i1 * i1;
-        rb[0] += (dbx * (jx[0] + 0.5 * g0x[0]) + dby * (jy[0] + 0.5 * g0y[0])) * i0 * i0;
-    }
-    // force adjoint, local part: G0 = -rho grad phi (+ theta grad rho)
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        rb[c] -= g0bx[c] * dpx[c] + g0by[c] * dpy[c];
-        F.rhob_loc[(int64_t)c * N + s] = rb[c];
-        F.jb[(int64_t)(2 * c) * N + s] = jbx[c];
-        F.jb[(int64_t)(2 * c + 1) * N + s] = jby[c];
-        F.av[(int64_t)(2 * c) * N + s] = rho[c] * g0bx[c];
-        F.av[(int64_t)(2 * c + 1) * N + s] = rho[c] * g0by[c];
-        F.bv[(int64_t)(2 * c) * N + s] = k.force == 0 ? g0bx[c] : 0.0;
-        F.bv[(int64_t)(2 * c + 1) * N + s] = k.force == 0 ? g0by[c] : 0.0;
-    }
+    return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
 // Discrete divergence with the gradient stencil: sum_i 3 w_i v_i . V(x + v_i)
-// (the transpose of the gradient up to a sign).
+// (the transpose of the gradient up to a sign), on global fields.
 __device__ __forceinline__ double div9(const double* vx, const double* vy, const Geometry& g, int x, int y) {
-    const int xm = wrapg(x - 1, g.nx), xp = wrapg(x + 1, g.nx), ym = wrapg(y - 1, g.ny), yp = wrapg(y + 1, g.ny);
+    const int xm = wrapg(x - 1, g.nx, g.wrap_general), xp = wrapg(x + 1, g.nx, g.wrap_general), ym = wrapg(y - 1, g.ny, g.wrap_general), yp = wrapg(y + 1, g.ny, g.wrap_general);
     const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
     const double ax = 4.0 * (vx[r0 + xp] - vx[r0 + xm]) + ((vx[rp + xp] - vx[rp + xm]) + (vx[rm + xp] - vx[rm + xm]));
     const double ay = 4.0 * (vy[rp + x] - vy[rm + x]) + ((vy[rp + xp] + vy[rp + xm]) - (vy[rm + xm] + vy[rm + xp]));
     return (ax + ay) * (1.0 / 12.0);
 }
 
+// The same divergence on LDS arrays with row stride S (identical arithmetic).
+template <int S>
+__device__ __forceinline__ double div9s(const double* vx, const double* vy, int ex, int ey) {
+    const double* a = vx + ey * S + ex;
+    const double* b = vy + ey * S + ex;
+    const double ax = 4.0 * (a[1] - a[-1]) + ((a[S + 1] - a[S - 1]) + (a[-S + 1] - a[-S - 1]));
+    const double ay = 4.0 * (b[S] - b[-S]) + ((b[S + 1] + b[S - 1]) - (b[-S - 1] + b[-S + 1]));
+    return (ax + ay) * (1.0 / 12.0);
+}
+
+// Isotropic Laplacian on a global field (the arithmetic of lap9s).
 __device__ __forceinline__ double lapg(const double* a, const Geometry& g, int x, int y) {
-    const int xm = wrapg(x - 1, g.nx), xp = wrapg(x + 1, g.nx), ym = wrapg(y - 1, g.ny), yp = wrapg(y + 1, g.ny);
+    const int xm = wrapg(x - 1, g.nx, g.wrap_general), xp = wrapg(x + 1, g.nx, g.wrap_general), ym = wrapg(y - 1, g.ny, g.wrap_general), yp = wrapg(y + 1, g.ny, g.wrap_general);
     const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
     const double axis = (a[r0 + xp] + a[r0 + xm]) + (a[rp + x] + a[rm + x]);
     const double diag = (a[rp + xp] + a[rp + xm]) + (a[rm + xm] + a[rm + xp]);
     return (4.0 * axis + diag - 20.0 * a[r0 + x]) * (1.0 / 6.0);
 }
 
-// Kernel CA: the un-stream of step t (kernel C) fused with kernel A of step
-// t - 1.  The cotangent kernel C would scatter from site x to x - v_i is
-// gathered here: site y takes (1 - omega) fb_i(y + v_i) + rhob(y + v_i) +
-// jb(y + v_i).v_i, with rhob = rhob_loc + rhob_b + Lap^T(lb_tot) and jb of step
-// t computed for the tile and a ring of radius 1 in LDS; the result is
-// written (the next step's C part reads it at neighbours) and used at once as
-// the incoming cotangent of step t - 1.  Fc holds step t's fields, F step
-// t - 1's (rhob_loc and jb are double-buffered by step parity, since other
-// workgroups still read step t's values around their tiles).
+// Local part of the adjoint at one site (collision, friction, force):
+// given the incoming cotangent fin of the site's new populations, its forward
+// moments (rho, j), the potential gradient (dpx, dpy) and the density gradient
+// (rx, ry), the local density and momentum cotangents rb, jb, the vectors
+// av = rho G0b, bv = G0b (log forcing; 0 for nid) and the Laplacian cotangent
+// lb of the correction term.
 template <int C>
-__global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fbn, double* __restrict__ fbo,
-                                                   Geometry g, Coeffs<C> k, Fields Fc, Fields F) {
-    constexpr int EX = TX + 4, EY = TY + 4, MX = TX + 2, MY = TY + 2, NT = TX * TY;
-    __shared__ double s_rho[C][EY * EX];
-    __shared__ double s_phi[C][MY * MX];
-    __shared__ double s_rb[C][MY * MX];
-    __shared__ double s_jx[C][MY * MX];
-    __shared__ double s_jy[C][MY * MX];
-    const int N = g.nx * g.ny;
-    const int tiles_x = (g.nx + TX - 1) / TX;
-    const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
-    for (int e = threadIdx.x; e < EX * EY; e += NT) {
-        const int ey = e / EX, ex = e - ey * EX;
-        const int s = wrapg(y0 - 2 + ey, g.ny) * g.nx + wrapg(x0 - 2 + ex, g.nx);
-#pragma unroll
-        for (int c = 0; c < C; ++c) s_rho[c][e] = F.rho[(int64_t)c * N + s];
-    }
-    for (int m = threadIdx.x; m < MX * MY; m += NT) {  // kernel C's per-site terms of step t, radius 1
-        const int my = m / MX, mx = m - my * MX;
-        const int xx = wrapg(x0 - 1 + mx, g.nx), yy = wrapg(y0 - 1 + my, g.ny);
-        const int e = yy * g.nx + xx;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s_rb[c][m] = Fc.rhob_loc[(int64_t)c * N + e] + Fc.rhob_b[(int64_t)c * N + e] +
-                         lapg(Fc.lb_tot + (int64_t)c * N, g, xx, yy);
-            s_jx[c][m] = Fc.jb[(int64_t)(2 * c) * N + e];
-            s_jy[c][m] = Fc.jb[(int64_t)(2 * c + 1) * N + e];
-        }
-    }
-    __syncthreads();
-    for (int m = threadIdx.x; m < MX * MY; m += NT) {
-        const int my = m / MX, mx = m - my * MX;
-        double r[C], l[C], ph[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
-            l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
-        }
-        potential<double, C>(r, l, k, ph);
-#pragma unroll
-        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= g.nx || y >= g.ny) return;
-    const int s = y * g.nx + x;
+__device__ __forceinline__ void adjoint_local(const double (&fin)[C][Q], const double (&rho)[C], const double (&jx)[C],
+                                              const double (&jy)[C], const double (&dpx)[C], const double (&dpy)[C],
+                                              const double (&rx)[C], const double (&ry)[C], const Coeffs<C>& k,
+                                              double (&rb)[C], double (&jbx)[C], double (&jby)[C], double (&avx)[C],
+                                              double (&avy)[C], double (&bvx)[C], double (&bvy)[C], double (&lb)[C]) {
     const double omega = k.omega, cG = k.cG, cL = k.cL;
-
-    // step t's un-streamed cotangent at this site = the incoming cotangent of step t - 1
-    double fin[C][Q];
+    double g0x[C], g0y[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int q = (ly + 1 + VY[i]) * MX + (lx + 1 + VX[i]);
-            const int src = wrapg(y + VY[i], g.ny) * g.nx + wrapg(x + VX[i], g.nx);
-            const double pb = (1.0 - omega) * fbn[((int64_t)i * g.plane + src) * C + c] + s_rb[c][q] +
-                              s_jx[c][q] * VX[i] + s_jy[c][q] * VY[i];
-            fin[c][i] = pb;
-            fbo[((int64_t)i * g.plane + s) * C + c] = pb;
-        }
-    }
-    double rho[C], jx[C], jy[C], g0x[C], g0y[C], dpx[C], dpy[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        rho[c] = F.rho[(int64_t)c * N + s];
-        jx[c] = F.mom[(int64_t)(2 * c) * N + s];
-        jy[c] = F.mom[(int64_t)(2 * c + 1) * N + s];
-        double rx, ry;
-        grad9s<double, MX>(s_phi[c], lx + 1, ly + 1, dpx[c], dpy[c]);
-        grad9s<double, EX>(s_rho[c], lx + 2, ly + 2, rx, ry);
         g0x[c] = -rho[c] * dpx[c];
         g0y[c] = -rho[c] * dpy[c];
         if (k.force == 0) {
-            g0x[c] += THETA * rx;
-            g0y[c] += THETA * ry;
+            g0x[c] += THETA * rx[c];
+            g0y[c] += THETA * ry[c];
         }
     }
     // forward friction (C = 2 closed form)
@@ -328,12 +138,14 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
         gx[c] = g0x[c];
         gy[c] = g0y[c];
     }
+    double ir[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ir[c] = recip(rho[c]);
     if constexpr (C == 2) {
-        const double lam = k.lam(0, 1);
-        m = rho[0] * rho[1] / (rho[0] + rho[1]);
-        K = lam / (1.0 + 0.5 * lam);
-        d0x = (jx[1] + 0.5 * g0x[1]) / rho[1] - (jx[0] + 0.5 * g0x[0]) / rho[0];
-        d0y = (jy[1] + 0.5 * g0y[1]) / rho[1] - (jy[0] + 0.5 * g0y[0]) / rho[0];
+        m = rho[0] * rho[1] * recip(rho[0] + rho[1]);
+        K = k.lam(0, 1) * k.fk;  // lambda / (1 + lambda/2)
+        d0x = (jx[1] + 0.5 * g0x[1]) * ir[1] - (jx[0] + 0.5 * g0x[0]) * ir[0];
+        d0y = (jy[1] + 0.5 * g0y[1]) * ir[1] - (jy[0] + 0.5 * g0y[0]) * ir[0];
         gx[0] += K * m * d0x;
         gx[1] -= K * m * d0x;
         gy[0] += K * m * d0y;
@@ -342,7 +154,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
 
     // collision adjoint: h = omega [rho M0 + 3 j.M + Q(j)/rho] + 3 G.M
     //                        + [2 G.B.j + cG Q(G)]/rho + cL L tr B
-    double rb[C], jbx[C], jby[C], gbx[C], gby[C];
+    double gbx[C], gby[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         double M0 = 0, Mx = 0, My = 0, Mxx = 0, Myy = 0, Mxy = 0;
@@ -359,7 +171,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
             Mxy += fb * vx * vy;
         }
         const double Bxx = 4.5 * Mxx - 1.5 * M0, Byy = 4.5 * Myy - 1.5 * M0, Bxy = 4.5 * Mxy;
-        const double r = rho[c], ri = 1.0 / r;
+        const double ri = ir[c];
         const double Jx = jx[c], Jy = jy[c], Gx = gx[c], Gy = gy[c];
         const double Qj = Bxx * Jx * Jx + Byy * Jy * Jy + 2.0 * Bxy * Jx * Jy;
         const double QG = Bxx * Gx * Gx + Byy * Gy * Gy + 2.0 * Bxy * Gx * Gy;
@@ -371,7 +183,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
         jby[c] = omega * (3.0 * My + 2.0 * BJy * ri) + 2.0 * BGy * ri;
         gbx[c] = 3.0 * Mx + 2.0 * (BJx + cG * BGx) * ri;
         gby[c] = 3.0 * My + 2.0 * (BJy + cG * BGy) * ri;
-        F.lb[(int64_t)c * N + s] = cL * (Bxx + Byy);
+        lb[c] = cL * (Bxx + Byy);
     }
     // friction adjoint: G = G0 + (+-) K m d0
     double g0bx[C], g0by[C];
@@ -384,11 +196,11 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
         const double gfbx = gbx[0] - gbx[1], gfby = gby[0] - gby[1];
         const double mb = K * (gfbx * d0x + gfby * d0y);
         const double dbx = K * m * gfbx, dby = K * m * gfby;
-        const double s2 = (rho[0] + rho[1]) * (rho[0] + rho[1]);
-        rb[0] += mb * rho[1] * rho[1] / s2;
-        rb[1] += mb * rho[0] * rho[0] / s2;
+        const double is = recip(rho[0] + rho[1]), is2 = is * is;
+        rb[0] += mb * rho[1] * rho[1] * is2;
+        rb[1] += mb * rho[0] * rho[0] * is2;
         // d0 = (j1 + G0_1/2)/rho1 - (j0 + G0_0/2)/rho0, per axis
-        const double i0 = 1.0 / rho[0], i1 = 1.0 / rho[1];
+        const double i0 = ir[0], i1 = ir[1];
         jbx[1] += dbx * i1;
         jbx[0] -= dbx * i0;
         jby[1] += dby * i1;
@@ -404,72 +216,64 @@ __global__ void __launch_bounds__(TX* TY) k_adj_ca(const double* __restrict__ fb
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         rb[c] -= g0bx[c] * dpx[c] + g0by[c] * dpy[c];
-        F.rhob_loc[(int64_t)c * N + s] = rb[c];
-        F.jb[(int64_t)(2 * c) * N + s] = jbx[c];
-        F.jb[(int64_t)(2 * c + 1) * N + s] = jby[c];
-        F.av[(int64_t)(2 * c) * N + s] = rho[c] * g0bx[c];
-        F.av[(int64_t)(2 * c + 1) * N + s] = rho[c] * g0by[c];
-        F.bv[(int64_t)(2 * c) * N + s] = k.force == 0 ? g0bx[c] : 0.0;
-        F.bv[(int64_t)(2 * c + 1) * N + s] = k.force == 0 ? g0by[c] : 0.0;
+        avx[c] = rho[c] * g0bx[c];
+        avy[c] = rho[c] * g0by[c];
+        bvx[c] = k.force == 0 ? g0bx[c] : 0.0;
+        bvy[c] = k.force == 0 ? g0by[c] : 0.0;
     }
 }
 
-// Kernel B: potential adjoint and parameter cotangents (one partial vector
-// per workgroup, reduced in a fixed order).
-template <int C>
-__global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F, double* __restrict__ partial) {
-    constexpr int NP = n_params(C);
-    __shared__ double s_red[NP][BLK];
-    const int N = g.nx * g.ny;
-    const int s = blockIdx.x * BLK + threadIdx.x;
-    double acc[NP];
+// Potential part of the adjoint at one site: given rho, its Laplacian L,
+// phib = div(av), dbv = div(bv) (log forcing) and the local Laplacian
+// cotangent lb, the density cotangent rhob_b and the total Laplacian
+// cotangent lb_tot; with ACC, adds the site's parameter cotangents to acc.
+template <int C, bool ACC>
+__device__ __forceinline__ void adjoint_potential(const double (&rho)[C], const double (&L)[C], const double (&phib)[C],
+                                                  const double (&dbv)[C], const double (&lb)[C], const Coeffs<C>& k,
+                                                  double (&rhob_b)[C], double (&lb_tot)[C], double* acc) {
+    double mub[C], rb[C];
+    double eta = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-    if (s < N) {
-        const int y = s / g.nx, x = s - y * g.nx;
-        double rho[C], L[C], mub[C], rb[C];
-        double eta = 0, tot = 0;
+    for (int c = 0; c < C; ++c) {
+        eta += k.b[c] * rho[c];
+        tot += rho[c];
+    }
+    const double fv = 1.0 - eta, iv = recip(fv);
+    double ir[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            rho[c] = F.rho[(int64_t)c * N + s];
-            L[c] = lapg(F.rho + (int64_t)c * N, g, x, y);
-            eta += k.b[c] * rho[c];
-            tot += rho[c];
-        }
-        const double fv = 1.0 - eta, iv = 1.0 / fv;
+    for (int c = 0; c < C; ++c) {
+        ir[c] = recip(rho[c]);
+        mub[c] = k.gamma * phib[c];
+        rb[c] = 0.0;
+        if (k.force == 0)
+            rb[c] -= THETA * dbv[c];
+        else
+            rb[c] -= THETA * phib[c] * ir[c];
+    }
+    // d mu^c / d rho^d = kT [delta/rho^c + (b^c + b^d)/(1-eta) + b^c b^d tot/(1-eta)^2] - 2 a^{cd}
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const double phib = div9(F.av + (int64_t)(2 * c) * N, F.av + (int64_t)(2 * c + 1) * N, g, x, y);
-            mub[c] = k.gamma * phib;
-            rb[c] = 0.0;
-            if (k.force == 0)
-                rb[c] -= THETA * div9(F.bv + (int64_t)(2 * c) * N, F.bv + (int64_t)(2 * c + 1) * N, g, x, y);
-            else
-                rb[c] -= THETA * phib / rho[c];
-        }
-        // d mu^c / d rho^d = kT [delta/rho^c + (b^c + b^d)/(1-eta) + b^c b^d tot/(1-eta)^2] - 2 a^{cd}
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int d = 0; d < C; ++d) {
-                double J = k.kT * ((k.b[c] + k.b[d]) * iv + k.b[c] * k.b[d] * tot * iv * iv) - k.a2(c, d);
-                if (c == d) J += k.kT / rho[c];
-                rb[d] += mub[c] * J;
-            }
+    for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int d = 0; d < C; ++d) {
-            double lt = F.lb[(int64_t)d * N + s];
-#pragma unroll
-            for (int c = 0; c < C; ++c) lt -= mub[c] * k.kap(c, d);
-            F.lb_tot[(int64_t)d * N + s] = lt;
-            F.rhob_b[(int64_t)d * N + s] = rb[d];
+            double J = k.kT * ((k.b[c] + k.b[d]) * iv + k.b[c] * k.b[d] * tot * iv * iv) - k.a2(c, d);
+            if (c == d) J += k.kT * ir[c];
+            rb[d] += mub[c] * J;
         }
+#pragma unroll
+    for (int d = 0; d < C; ++d) {
+        double lt = lb[d];
+#pragma unroll
+        for (int c = 0; c < C; ++c) lt -= mub[c] * k.kap(c, d);
+        lb_tot[d] = lt;
+        rhob_b[d] = rb[d];
+    }
+    if constexpr (ACC) {
         // parameter cotangents of mu^c = kT [ln(rho^c/(1-eta)) + b^c tot/(1-eta)]
         //                                 - sum_d (2 a^{cd} rho^d + kappa^{cd} L^d)
         const int oa = 1, ob = 1 + C * (C + 1) / 2, ok = ob + C;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            acc[0] += mub[c] * (log(rho[c] * iv) + k.b[c] * tot * iv);
+            acc[0] += mub[c] * (dlog(rho[c] * iv) + k.b[c] * tot * iv);
 #pragma unroll
             for (int d = 0; d < C; ++d) {
                 acc[oa + pair_index(C, c, d)] -= 2.0 * mub[c] * rho[d];
@@ -483,16 +287,342 @@ __global__ void __launch_bounds__(BLK) k_adj_b(Geometry g, Coeffs<C> k, Fields F
             }
         }
     }
+}
+
+// Tree reduction of the per-thread parameter cotangents of a workgroup (NT
+// threads, fixed order: at each level h = NT/2, ..., 1 thread t < h adds
+// thread t + h's value) into one partial vector.  The levels that cross
+// wavefronts go through LDS; the last six run within wavefront 0 by shuffles,
+// with the same pairs in the same order.  Every thread must call it.
+template <int NP, int NT>
+__device__ __forceinline__ void reduce_partial(double (&s_red)[NP][NT], const double (&acc)[NP],
+                                               double* __restrict__ out) {
+    static_assert(NT % 64 == 0 && NT >= 64, "whole wavefronts");
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) s_red[q][threadIdx.x] = acc[q];
+    for (int q = 0; q < NP; ++q) s_red[q][t] = acc[q];
     __syncthreads();
-    for (int h = BLK / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
+    for (int h = NT / 2; h >= 64; h >>= 1) {
+        if (t < h)
 #pragma unroll
-            for (int q = 0; q < NP; ++q) s_red[q][threadIdx.x] += s_red[q][threadIdx.x + h];
+            for (int q = 0; q < NP; ++q) s_red[q][t] += s_red[q][t + h];
         __syncthreads();
     }
-    if (threadIdx.x < NP) partial[(int64_t)blockIdx.x * NP + threadIdx.x] = s_red[threadIdx.x][0];
+    if (t < 64) {
+        double v[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v[q] = s_red[q][t];
+#pragma unroll
+        for (int h = 32; h > 0; h >>= 1)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) v[q] += __shfl_down(v[q], h, 64);
+        if (t == 0)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) out[q] = v[q];
+    }
+}
+
+// Tile origin of workgroup b (row-major tiles).
+__device__ __forceinline__ void tile_origin(const Geometry& g, int& x0, int& y0) {
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    x0 = (blockIdx.x % tiles_x) * TX;
+    y0 = (blockIdx.x / tiles_x) * TY;
+}
+
+// Writes the local adjoint of one site into the step's fields.
+template <int C>
+__device__ __forceinline__ void store_local(const Fields& F, int64_t N, int s, const double (&rb)[C],
+                                            const double (&jbx)[C], const double (&jby)[C], const double (&avx)[C],
+                                            const double (&avy)[C], const double (&bvx)[C], const double (&bvy)[C],
+                                            const double (&lb)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        F.rhob_loc[c * N + s] = rb[c];
+        F.jb[(2 * c) * N + s] = jbx[c];
+        F.jb[(2 * c + 1) * N + s] = jby[c];
+        F.av[(2 * c) * N + s] = avx[c];
+        F.av[(2 * c + 1) * N + s] = avy[c];
+        F.bv[(2 * c) * N + s] = bvx[c];
+        F.bv[(2 * c + 1) * N + s] = bvy[c];
+        F.lb[c * N + s] = lb[c];
+    }
+}
+
+// Stages step t's densities on the tile plus a radius-2 ring (s_rho, row
+// stride TX + 4).
+template <int C>
+__device__ __forceinline__ void stage_rho(const Fields& F, const Geometry& g, int x0, int y0,
+                                          double (&s_rho)[C][(TX + 4) * (TY + 4)]) {
+    constexpr int EX = TX + 4, EY = TY + 4, NT = TX * TY;
+    const int64_t N = (int64_t)g.nx * g.ny;
+    for (int e = threadIdx.x; e < EX * EY; e += NT) {
+        const int ey = e / EX, ex = e - ey * EX;
+        const int s = wrapg(y0 - 2 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + ex, g.nx, g.wrap_general);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_rho[c][e] = F.rho[c * N + s];
+    }
+}
+
+// The potential phi on the tile plus a radius-1 ring (s_phi, row stride
+// TX + 2) from the staged densities.
+template <int C>
+__device__ __forceinline__ void eval_potential(const Coeffs<C>& k, const double (&s_rho)[C][(TX + 4) * (TY + 4)],
+                                               double (&s_phi)[C][(TX + 2) * (TY + 2)]) {
+    constexpr int EX = TX + 4, MX = TX + 2, MY = TY + 2, NT = TX * TY;
+    for (int m = threadIdx.x; m < MX * MY; m += NT) {
+        const int my = m / MX, mx = m - my * MX;
+        double r[C], l[C], ph[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            r[c] = s_rho[c][(my + 1) * EX + mx + 1];
+            l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
+        }
+        potential<double, C>(r, l, k, ph);
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+    }
+}
+
+// Forward moments of site s.
+template <int C>
+__device__ __forceinline__ void load_moments(const Fields& F, int64_t N, int s, double (&rho)[C], double (&jx)[C],
+                                             double (&jy)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        rho[c] = F.rho[c * N + s];
+        jx[c] = F.mom[(2 * c) * N + s];
+        jy[c] = F.mom[(2 * c + 1) * N + s];
+    }
+}
+
+// Potential and density gradients at interior site (lx, ly) of the tile.
+template <int C>
+__device__ __forceinline__ void local_stencils(int lx, int ly, const double (&s_rho)[C][(TX + 4) * (TY + 4)],
+                                               const double (&s_phi)[C][(TX + 2) * (TY + 2)], double (&dpx)[C],
+                                               double (&dpy)[C], double (&rx)[C], double (&ry)[C]) {
+    constexpr int EX = TX + 4, MX = TX + 2;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        grad9s<double, MX>(s_phi[c], lx + 1, ly + 1, dpx[c], dpy[c]);
+        grad9s<double, EX>(s_rho[c], lx + 2, ly + 2, rx[c], ry[c]);
+    }
+}
+
+// Kernel A: collision, friction and force adjoint at each site of a tile,
+// from the cotangent fbn of the step's new state at the same site.
+template <int C>
+__global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn, Geometry g, Coeffs<C> k,
+                                                  Fields F) {
+    __shared__ double s_rho[C][(TX + 4) * (TY + 4)];
+    __shared__ double s_phi[C][(TX + 2) * (TY + 2)];
+    const int64_t N = (int64_t)g.nx * g.ny;
+    int x0, y0;
+    tile_origin(g, x0, y0);
+    stage_rho<C>(F, g, x0, y0, s_rho);
+    __syncthreads();
+    eval_potential<C>(k, s_rho, s_phi);
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = y * g.nx + x;
+    double fin[C][Q];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fin[c][i] = fbn[((int64_t)i * g.plane + s) * C + c];
+    double rho[C], jx[C], jy[C], dpx[C], dpy[C], rx[C], ry[C];
+    load_moments<C>(F, N, s, rho, jx, jy);
+    local_stencils<C>(lx, ly, s_rho, s_phi, dpx, dpy, rx, ry);
+    double rb[C], jbx[C], jby[C], avx[C], avy[C], bvx[C], bvy[C], lb[C];
+    adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+    store_local<C>(F, N, s, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+}
+
+// Kernel B: potential adjoint and parameter cotangents of each site of a tile
+// (one partial vector per tile, reduced in a fixed order).
+template <int C>
+__global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Fields F, double* __restrict__ partial) {
+    constexpr int NP = n_params(C), NT = TX * TY;
+    __shared__ double s_red[NP][NT];
+    const int64_t N = (int64_t)g.nx * g.ny;
+    int x0, y0;
+    tile_origin(g, x0, y0);
+    const int x = x0 + (int)threadIdx.x % TX, y = y0 + (int)threadIdx.x / TX;
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const int s = y * g.nx + x;
+        double rho[C], L[C], phib[C], dbv[C], lb[C], rbb[C], lbt[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rho[c] = F.rho[c * N + s];
+            L[c] = lapg(F.rho + c * N, g, x, y);
+            phib[c] = div9(F.av + (2 * c) * N, F.av + (2 * c + 1) * N, g, x, y);
+            dbv[c] = k.force == 0 ? div9(F.bv + (2 * c) * N, F.bv + (2 * c + 1) * N, g, x, y) : 0.0;
+            lb[c] = F.lb[c * N + s];
+        }
+        adjoint_potential<C, true>(rho, L, phib, dbv, lb, k, rbb, lbt, acc);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            F.lb_tot[c * N + s] = lbt[c];
+            F.rhob_b[c * N + s] = rbb[c];
+        }
+    }
+    reduce_partial<NP, NT>(s_red, acc, partial + (int64_t)blockIdx.x * NP);
+}
+
+// The fused kernel of one reversed step: B and C of step t + 1 and (with
+// DO_A) A of step t, on one tile.  Kernel B's outputs are needed by C on the
+// tile plus a radius-1 ring (the gather of the un-stream) and, through the
+// Laplacian of lb_tot, on a radius-2 ring: B is evaluated there from step
+// t + 1's fields staged in LDS on a radius-3 ring (its stencils reach one
+// further); ring sites are evaluated by several workgroups with the same
+// arithmetic, and only a tile's own sites add to its parameter partial, in
+// kernel B's order.  Then C's gather at each site gives the cotangent of
+// step t's new state (written to fbo) and, with DO_A, A of step t runs on it
+// at once.  Results equal the sequence A, B, C bit for bit.
+template <int C, bool DO_A>
+__global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ fbn, double* __restrict__ fbo,
+                                                    Geometry g, Coeffs<C> k, Fields Fn, Fields F,
+                                                    double* __restrict__ partial) {
+    constexpr int NT = TX * TY, NP = n_params(C);
+    constexpr int X3 = TX + 6, Y3 = TY + 6, X2 = TX + 4, Y2 = TY + 4, X1 = TX + 2, Y1 = TY + 2;
+    constexpr int RING2 = X2 * Y2 - TX * TY;
+    static_assert(RING2 <= NT, "one radius-2 ring site per thread");
+    __shared__ double s_av[2 * C][X3 * Y3];
+    __shared__ double s_bv[2 * C][X3 * Y3];
+    __shared__ double s_rn[C][X3 * Y3];  // densities of step t + 1
+    __shared__ double s_rbb[C][X2 * Y2];
+    __shared__ double s_lbt[C][X2 * Y2];
+    __shared__ double s_rb[C][X1 * Y1];
+    __shared__ double s_jx[C][X1 * Y1];
+    __shared__ double s_jy[C][X1 * Y1];
+    __shared__ double s_red[NP][NT];
+    __shared__ double s_rho[DO_A ? C : 1][(TX + 4) * (TY + 4)];
+    __shared__ double s_phi[DO_A ? C : 1][(TX + 2) * (TY + 2)];
+    const int64_t N = (int64_t)g.nx * g.ny;
+    int x0, y0;
+    tile_origin(g, x0, y0);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inside = x < g.nx && y < g.ny;
+    const int xw = wrapg(x, g.nx, g.wrap_general), yw = wrapg(y, g.ny, g.wrap_general);
+    const int s = yw * g.nx + xw;  // this thread's tile site (wrapped when outside the lattice)
+    int ring_ex = 0, ring_ey = 0;
+    const bool has_ring = (int)threadIdx.x < RING2;
+    if (has_ring) ring_coords<TX, TY>(threadIdx.x, ring_ex, ring_ey);
+    const int ring_s = wrapg(y0 - 2 + ring_ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + ring_ex, g.nx, g.wrap_general);
+
+    // Every global read first, so that their latencies overlap: step t + 1's
+    // fields around the tile into LDS; into registers the Laplacian cotangent
+    // of the sites this thread evaluates B at, the cotangents the gather
+    // takes from the neighbours, and step t's moments at the own site.
+    for (int e = threadIdx.x; e < X3 * Y3; e += NT) {
+        const int ey = e / X3, ex = e - ey * X3;
+        const int q = wrapg(y0 - 3 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 3 + ex, g.nx, g.wrap_general);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_rn[c][e] = Fn.rho[c * N + q];
+            s_av[2 * c][e] = Fn.av[(2 * c) * N + q];
+            s_av[2 * c + 1][e] = Fn.av[(2 * c + 1) * N + q];
+            if (k.force == 0) {
+                s_bv[2 * c][e] = Fn.bv[(2 * c) * N + q];
+                s_bv[2 * c + 1][e] = Fn.bv[(2 * c + 1) * N + q];
+            }
+        }
+    }
+    for (int m = threadIdx.x; m < X1 * Y1; m += NT) {
+        const int my = m / X1, mx = m - my * X1;
+        const int q = wrapg(y0 - 1 + my, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 1 + mx, g.nx, g.wrap_general);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_rb[c][m] = Fn.rhob_loc[c * N + q];
+            s_jx[c][m] = Fn.jb[(2 * c) * N + q];
+            s_jy[c][m] = Fn.jb[(2 * c + 1) * N + q];
+        }
+    }
+    if constexpr (DO_A) stage_rho<C>(F, g, x0, y0, s_rho);
+    double lb_own[C], lb_ring[C], fb_nb[C][Q], rho[C], jx[C], jy[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        lb_own[c] = Fn.lb[c * N + s];
+        lb_ring[c] = has_ring ? Fn.lb[c * N + ring_s] : 0.0;
+    }
+    if (inside) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int src = wrapg(y + VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x + VX[i], g.nx, g.wrap_general);
+                fb_nb[c][i] = fbn[((int64_t)i * g.plane + src) * C + c];
+            }
+        if constexpr (DO_A) load_moments<C>(F, N, s, rho, jx, jy);
+    }
+    __syncthreads();
+
+    // A's potential of step t, and B of step t + 1 on the tile (own site, with
+    // the parameter partial when it lies in the lattice) and on the radius-2
+    // ring around it
+    if constexpr (DO_A) eval_potential<C>(k, s_rho, s_phi);
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    auto b_site = [&](int ex, int ey, const double (&lb)[C], bool own) {  // ex, ey: position in the radius-2 grid
+        const int e3 = (ey + 1) * X3 + ex + 1, e2 = ey * X2 + ex;
+        double rn[C], L[C], phib[C], dbv[C], rbb[C], lbt[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rn[c] = s_rn[c][e3];
+            L[c] = lap9s<double, X3>(s_rn[c], ex + 1, ey + 1);
+            phib[c] = div9s<X3>(s_av[2 * c], s_av[2 * c + 1], ex + 1, ey + 1);
+            dbv[c] = k.force == 0 ? div9s<X3>(s_bv[2 * c], s_bv[2 * c + 1], ex + 1, ey + 1) : 0.0;
+        }
+        if (own)
+            adjoint_potential<C, true>(rn, L, phib, dbv, lb, k, rbb, lbt, acc);
+        else
+            adjoint_potential<C, false>(rn, L, phib, dbv, lb, k, rbb, lbt, nullptr);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_rbb[c][e2] = rbb[c];
+            s_lbt[c][e2] = lbt[c];
+        }
+    };
+    b_site(lx + 2, ly + 2, lb_own, inside);
+    if (has_ring) b_site(ring_ex, ring_ey, lb_ring, false);
+    __syncthreads();
+    // C of step t + 1: total density cotangent on the tile and a radius-1 ring
+    for (int m = threadIdx.x; m < X1 * Y1; m += NT) {
+        const int my = m / X1, mx = m - my * X1;
+        const int e2 = (my + 1) * X2 + mx + 1;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s_rb[c][m] = (s_rb[c][m] + s_rbb[c][e2]) + lap9s<double, X2>(s_lbt[c], mx + 1, my + 1);
+    }
+    reduce_partial<NP, NT>(s_red, acc, partial + (int64_t)blockIdx.x * NP);  // its first barrier orders s_rb
+    if (!inside) return;
+    const double omega = k.omega;
+    // the un-streamed cotangent at this site: step t's incoming cotangent
+    double fin[C][Q];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int q = (ly + 1 + VY[i]) * X1 + (lx + 1 + VX[i]);
+            const double pb =
+                (1.0 - omega) * fb_nb[c][i] + s_rb[c][q] + s_jx[c][q] * VX[i] + s_jy[c][q] * VY[i];
+            fin[c][i] = pb;
+            fbo[((int64_t)i * g.plane + s) * C + c] = pb;
+        }
+    }
+    if constexpr (DO_A) {
+        double dpx[C], dpy[C], rx[C], ry[C];
+        local_stencils<C>(lx, ly, s_rho, s_phi, dpx, dpy, rx, ry);
+        double rb[C], jbx[C], jby[C], avx[C], avy[C], bvx[C], bvy[C], lb[C];
+        adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+        store_local<C>(F, N, s, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+    }
 }
 
 // Fixed-order reduction of the per-workgroup partials of a whole segment
@@ -529,7 +659,7 @@ __global__ void __launch_bounds__(BLK) k_adj_c(const double* __restrict__ fbn, d
         for (int i = 0; i < Q; ++i) {
             const double pb = (1.0 - omega) * fbn[((int64_t)i * g.plane + s) * C + c] + rb + jbx * VX[i] +
                               jby * VY[i];
-            const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
+            const int t = wrapg(y - VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x - VX[i], g.nx, g.wrap_general);
             fbo[((int64_t)i * g.plane + t) * C + c] = pb;
         }
     }
@@ -551,7 +681,7 @@ __global__ void __launch_bounds__(BLK) k_moments_adj(const double* __restrict__ 
         const double jby = momb ? momb[(int64_t)(2 * c + 1) * N + s] : 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int t = wrapg(y - VY[i], g.ny) * g.nx + wrapg(x - VX[i], g.nx);
+            const int t = wrapg(y - VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x - VX[i], g.nx, g.wrap_general);
             fb[((int64_t)i * g.plane + t) * C + c] = rb + jbx * VX[i] + jby * VY[i];
         }
     }
@@ -570,10 +700,18 @@ void vdwlb::release_adjoint_graph(vdwlb_plan& p) {
 
 namespace {
 
+// Geometry of the reverse kernels: their indices reach 3 sites beyond a tile,
+// so the cheap periodic wrap needs extents larger than a tile by that much.
+Geometry adjoint_geometry(const vdwlb_plan& p) {
+    Geometry g = make_geometry(p, adj::TX, adj::TY);
+    g.wrap_general = (p.nx < adj::TX + 8 || p.ny < adj::TY + 8) ? 1 : 0;
+    return g;
+}
+
 struct Layout {
     int64_t N, plane, state;  // elements
     int64_t f0, f1, fb, moms, fields, partial, total;
-    int nb_b, np;
+    int tiles, np;
 };
 
 Layout layout(const vdwlb_plan& p, int nsteps) {
@@ -582,7 +720,7 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
     L.plane = p.plane;
     L.state = (int64_t)Q * p.C * p.plane;
     L.np = adj::n_params(p.C);
-    L.nb_b = (int)((L.N + adj::BLK - 1) / adj::BLK);
+    L.tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
     int64_t o = 0;
     L.f0 = o;
     o += L.state;
@@ -593,29 +731,30 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
     L.moms = o;
     o += (int64_t)nsteps * 3 * p.C * L.N;
     L.fields = o;
-    o += 13 * (int64_t)p.C * L.N;
-    L.partial = o;  // one partial vector per workgroup of kernel B and per step
-    o += (int64_t)nsteps * L.nb_b * L.np;
+    o += 18 * (int64_t)p.C * L.N;
+    L.partial = o;  // one partial vector per tile and per step
+    o += (int64_t)nsteps * L.tiles * L.np;
     L.total = o;
     return L;
 }
 
+// Fields of step t: the moments of its forward recompute, and the adjoint
+// fields, those read around a tile by the next kernel (rhob_loc, jb, av, bv,
+// lb) by step parity.
 adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
     adj::Fields F;
-    const int C = p.C;
-    const double* mom0 = ws + L.moms + (int64_t)t * 3 * C * L.N;
+    const int64_t CN = (int64_t)p.C * L.N;
+    const double* mom0 = ws + L.moms + (int64_t)t * 3 * CN;
     F.rho = mom0;
-    F.mom = mom0 + (int64_t)C * L.N;
-    double* f = ws + L.fields;
-    // rhob_loc and jb by step parity (the fused kernel reads step t's values
-    // around its tile while it writes step t - 1's)
-    F.rhob_loc = f + ((t & 1) ? 10 * (int64_t)C * L.N : 0);
-    F.jb = f + ((t & 1) ? 11 : 1) * (int64_t)C * L.N;
-    F.av = f + 3 * (int64_t)C * L.N;
-    F.bv = f + 5 * (int64_t)C * L.N;
-    F.lb = f + 7 * (int64_t)C * L.N;
-    F.rhob_b = f + 8 * (int64_t)C * L.N;
-    F.lb_tot = f + 9 * (int64_t)C * L.N;
+    F.mom = mom0 + CN;
+    double* f = ws + L.fields + ((t & 1) ? 8 * CN : 0);  // per parity: rhob_loc C, jb 2C, av 2C, bv 2C, lb C
+    F.rhob_loc = f;
+    F.jb = f + CN;
+    F.av = f + 3 * CN;
+    F.bv = f + 5 * CN;
+    F.lb = f + 7 * CN;
+    F.rhob_b = ws + L.fields + 16 * CN;
+    F.lb_tot = ws + L.fields + 17 * CN;
     return F;
 }
 
@@ -627,27 +766,32 @@ struct StepKernels {
     hipStream_t s;
     Geometry g;
     Coeffs<C> k;
-    int tiles;
     StepKernels(const vdwlb_plan& p_, const Layout& L_, double* ws_, hipStream_t s_)
-        : p(p_), L(L_), ws(ws_), s(s_), g(make_geometry(p_, adj::TX, adj::TY)), k(make_coeffs<C>(p_)) {
-        tiles = ((p.nx + adj::TX - 1) / adj::TX) * ((p.ny + adj::TY - 1) / adj::TY);
-    }
+        : p(p_), L(L_), ws(ws_), s(s_), g(adjoint_geometry(p_)), k(make_coeffs<C>(p_)) {}
+    double* partial_row(int t) const { return ws + L.partial + (int64_t)t * L.tiles * L.np; }
     void a(int t, const double* fbn) {
-        hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k,
+        hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k,
                            fields_at(p, L, ws, t));
     }
     void b(int t) {
-        hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, g, k, fields_at(p, L, ws, t),
-                           ws + L.partial + (int64_t)t * L.nb_b * L.np);
+        hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, g, k,
+                           fields_at(p, L, ws, t), partial_row(t));
     }
     void c(int t, const double* fbn, double* fbo) {
-        hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(L.nb_b), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega,
+        const int nb = (int)((L.N + adj::BLK - 1) / adj::BLK);
+        hipLaunchKernelGGL((adj::k_adj_c<C>), dim3(nb), dim3(adj::BLK), 0, s, fbn, fbo, g, k.omega,
                            fields_at(p, L, ws, t));
     }
-    // kernel C of step t + 1 fused with kernel A of step t
-    void ca(int t, const double* fbn, double* fbo) {
-        hipLaunchKernelGGL((adj::k_adj_ca<C>), dim3(tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
-                           fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t));
+    // B and C of step t + 1 fused with A of step t
+    void bca(int t, const double* fbn, double* fbo) {
+        hipLaunchKernelGGL((adj::k_adj_bca<C, true>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
+                           fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t), partial_row(t + 1));
+    }
+    // B and C of step 0
+    void bc(const double* fbn, double* fbo) {
+        const adj::Fields F0 = fields_at(p, L, ws, 0);
+        hipLaunchKernelGGL((adj::k_adj_bca<C, false>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
+                           F0, F0, partial_row(0));
     }
 };
 
@@ -657,8 +801,9 @@ bool adjoint_fused() {
 }
 
 // The reverse sweep of a segment from fbar_io; the result ends in bufs[n & 1].
-// Unfused: per step A, B, C.  Fused: A, B for the last step, then per earlier
-// step the fused C + A and B, and a final C.  Both compute the same values.
+// Unfused: per step A, B, C.  Fused: A of the last step, then one kernel per
+// earlier step (B and C of the step after it with its own A), and B and C of
+// the first step.  Both compute the same values bit for bit.
 template <int C>
 hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* const (&bufs)[2],
                          hipStream_t s, bool fused) {
@@ -671,14 +816,9 @@ hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int n
         }
         return hipGetLastError();
     }
-    for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
-        if (k == 0)
-            K.a(t, bufs[0]);
-        else
-            K.ca(t, bufs[(k - 1) & 1], bufs[k & 1]);
-        K.b(t);
-    }
-    K.c(0, bufs[(nsteps - 1) & 1], bufs[nsteps & 1]);
+    K.a(nsteps - 1, bufs[0]);
+    for (int t = nsteps - 2, k = 1; t >= 0; --t, ++k) K.bca(t, bufs[(k - 1) & 1], bufs[k & 1]);
+    K.bc(bufs[(nsteps - 1) & 1], bufs[nsteps & 1]);
     return hipGetLastError();
 }
 
@@ -704,7 +844,7 @@ hipError_t enqueue_reverse(const vdwlb_plan& p, const Layout& L, double* ws, int
                             : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
     if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
         hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
-                           nsteps * L.nb_b, L.np, pbar);
+                           nsteps * L.tiles, L.np, pbar);
         e = hipGetLastError();
     }
     if (e == hipSuccess && (nsteps & 1))
@@ -792,7 +932,7 @@ vdwlb_status check_adjoint(const vdwlb_plan* p, int32_t nsteps, const void* work
     if (!state_aligned(*p, workspace)) return VDWLB_E_INVALID_ARG;
     if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     const Layout L = layout(*p, nsteps);
-    if ((int64_t)nsteps * L.nb_b > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
+    if ((int64_t)nsteps * L.tiles > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
     return VDWLB_OK;
 }
 
@@ -811,7 +951,7 @@ vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const voi
                                    void* stream) {
     if (!p || !fbar || (!rho_bar && !mom_bar) || !state_aligned(*p, fbar)) return VDWLB_E_INVALID_ARG;
     if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
-    const Geometry g = make_geometry(*p, adj::TX, adj::TY);
+    const Geometry g = adjoint_geometry(*p);
     const int nb = (int)(((int64_t)p->nx * p->ny + adj::BLK - 1) / adj::BLK);
     hipError_t e = hipMemsetAsync(fbar, 0, vdwlb_state_bytes(p), (hipStream_t)stream);
     if (e != hipSuccess) return set_device_error(e, "moments adjoint");
