@@ -515,35 +515,58 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     if (has_ring) ring_coords<TX, TY>(threadIdx.x, ring_ex, ring_ey);
     const int ring_s = wrapg(y0 - 2 + ring_ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + ring_ex, g.nx, g.wrap_general);
 
-    // Every global read first, so that their latencies overlap: step t + 1's
-    // fields around the tile into LDS; into registers the Laplacian cotangent
-    // of the sites this thread evaluates B at, the cotangents the gather
-    // takes from the neighbours, and step t's moments at the own site.
-    for (int e = threadIdx.x; e < X3 * Y3; e += NT) {
-        const int ey = e / X3, ex = e - ey * X3;
-        const int q = wrapg(y0 - 3 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 3 + ex, g.nx, g.wrap_general);
+    // Every global read first, into registers, so that their latencies
+    // overlap (at one wavefront per SIMD each wait would otherwise be
+    // exposed): step t + 1's fields around the tile, step t's densities
+    // around it, the Laplacian cotangent of the sites this thread evaluates B
+    // at, the cotangents the gather takes from the neighbours and step t's
+    // moments at the own site; then the LDS stores.
+    constexpr int N3 = (X3 * Y3 + NT - 1) / NT, N1 = (X1 * Y1 + NT - 1) / NT;
+    constexpr int N2 = (X2 * Y2 + NT - 1) / NT;
+    double v3[N3][5 * C], v1[N1][3 * C], v2[N2][C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s_rn[c][e] = Fn.rho[c * N + q];
-            s_av[2 * c][e] = Fn.av[(2 * c) * N + q];
-            s_av[2 * c + 1][e] = Fn.av[(2 * c + 1) * N + q];
-            if (k.force == 0) {
-                s_bv[2 * c][e] = Fn.bv[(2 * c) * N + q];
-                s_bv[2 * c + 1][e] = Fn.bv[(2 * c + 1) * N + q];
+    for (int it = 0; it < N3; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < X3 * Y3) {
+            const int ey = e / X3, ex = e - ey * X3;
+            const int q = wrapg(y0 - 3 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 3 + ex, g.nx, g.wrap_general);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                v3[it][c] = Fn.rho[c * N + q];
+                v3[it][C + 2 * c] = Fn.av[(2 * c) * N + q];
+                v3[it][C + 2 * c + 1] = Fn.av[(2 * c + 1) * N + q];
+                v3[it][3 * C + 2 * c] = k.force == 0 ? Fn.bv[(2 * c) * N + q] : 0.0;
+                v3[it][3 * C + 2 * c + 1] = k.force == 0 ? Fn.bv[(2 * c + 1) * N + q] : 0.0;
             }
         }
     }
-    for (int m = threadIdx.x; m < X1 * Y1; m += NT) {
-        const int my = m / X1, mx = m - my * X1;
-        const int q = wrapg(y0 - 1 + my, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 1 + mx, g.nx, g.wrap_general);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s_rb[c][m] = Fn.rhob_loc[c * N + q];
-            s_jx[c][m] = Fn.jb[(2 * c) * N + q];
-            s_jy[c][m] = Fn.jb[(2 * c + 1) * N + q];
+    for (int it = 0; it < N1; ++it) {
+        const int m = threadIdx.x + it * NT;
+        if (m < X1 * Y1) {
+            const int my = m / X1, mx = m - my * X1;
+            const int q = wrapg(y0 - 1 + my, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 1 + mx, g.nx, g.wrap_general);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                v1[it][c] = Fn.rhob_loc[c * N + q];
+                v1[it][C + 2 * c] = Fn.jb[(2 * c) * N + q];
+                v1[it][C + 2 * c + 1] = Fn.jb[(2 * c + 1) * N + q];
+            }
         }
     }
-    if constexpr (DO_A) stage_rho<C>(F, g, x0, y0, s_rho);
+    if constexpr (DO_A) {
+#pragma unroll
+        for (int it = 0; it < N2; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < X2 * Y2) {
+                const int ey = e / X2, ex = e - ey * X2;
+                const int q =
+                    wrapg(y0 - 2 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + ex, g.nx, g.wrap_general);
+#pragma unroll
+                for (int c = 0; c < C; ++c) v2[it][c] = F.rho[c * N + q];
+            }
+        }
+    }
     double lb_own[C], lb_ring[C], fb_nb[C][Q], rho[C], jx[C], jy[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -555,10 +578,44 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const int src = wrapg(y + VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x + VX[i], g.nx, g.wrap_general);
+                const int src =
+                    wrapg(y + VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x + VX[i], g.nx, g.wrap_general);
                 fb_nb[c][i] = fbn[((int64_t)i * g.plane + src) * C + c];
             }
         if constexpr (DO_A) load_moments<C>(F, N, s, rho, jx, jy);
+    }
+#pragma unroll
+    for (int it = 0; it < N3; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < X3 * Y3)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                s_rn[c][e] = v3[it][c];
+                s_av[2 * c][e] = v3[it][C + 2 * c];
+                s_av[2 * c + 1][e] = v3[it][C + 2 * c + 1];
+                s_bv[2 * c][e] = v3[it][3 * C + 2 * c];
+                s_bv[2 * c + 1][e] = v3[it][3 * C + 2 * c + 1];
+            }
+    }
+#pragma unroll
+    for (int it = 0; it < N1; ++it) {
+        const int m = threadIdx.x + it * NT;
+        if (m < X1 * Y1)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                s_rb[c][m] = v1[it][c];
+                s_jx[c][m] = v1[it][C + 2 * c];
+                s_jy[c][m] = v1[it][C + 2 * c + 1];
+            }
+    }
+    if constexpr (DO_A) {
+#pragma unroll
+        for (int it = 0; it < N2; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < X2 * Y2)
+#pragma unroll
+                for (int c = 0; c < C; ++c) s_rho[c][e] = v2[it][c];
+        }
     }
     __syncthreads();
 
@@ -631,8 +688,20 @@ __global__ void __launch_bounds__(BLK) k_adj_reduce(const double* __restrict__ p
                                                      double* __restrict__ pbar) {
     __shared__ double s[BLK];
     const int q = blockIdx.x;
+    // each thread sums entries b = threadIdx.x + j BLK in increasing j; the
+    // loads of a chunk are issued together (terms past n add an exact 0)
+    constexpr int CH = 16;
     double a = 0.0;
-    for (int b = threadIdx.x; b < n; b += BLK) a += partial[(int64_t)b * np + q];
+    for (int b0 = threadIdx.x; b0 < n; b0 += CH * BLK) {
+        double v[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int b = b0 + j * BLK;
+            v[j] = b < n ? partial[(int64_t)b * np + q] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) a += v[j];
+    }
     s[threadIdx.x] = a;
     __syncthreads();
     for (int h = BLK / 2; h > 0; h >>= 1) {
