@@ -293,9 +293,23 @@ int64_t vdwlb_batch_offset(const vdwlb_batch* batch, int32_t k);
 int64_t vdwlb_batch_density_offset(const vdwlb_batch* batch, int32_t k);
 
 /* Launch shape of the persistent kernel: threads per workgroup (256 or 1024;
- * D2Q9 batches only) and resident workgroups (0 = as many as the device
- * holds, capped at n). */
+ * D2Q9 batches run step by step only) and resident workgroups (0 = as many as
+ * the device holds, capped at n). */
 vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* batch, int32_t threads, int32_t blocks);
+
+/* Temporal blocking of D2Q9 batches of height 4 with C <= 2:
+ * steps_per_block K in 2 .. 6 runs each instance in blocks of at most K
+ * steps, every block strip by strip: a strip of 64 - 6K columns, 3K columns
+ * on either side and the K intermediate states are held in LDS (each step's
+ * valid region shrinks by the 3 columns a step reaches), so that HBM traffic
+ * falls by about K; 0 selects the step-by-step kernel.  Results are bit-identical
+ * either way, and a run leaves its result in the same pool.  With blocking,
+ * an instance that becomes unphysical stops at the end of the block in which
+ * it did (its status word still records the first unphysical step).
+ * Batches that allow it are created with K = 3.  VDWLB_E_UNSUPPORTED for
+ * other batches or when the block does not fit the LDS of a workgroup;
+ * VDWLB_E_INVALID_ARG for other values of K. */
+vdwlb_status vdwlb_batch_set_blocking(vdwlb_batch* batch, int32_t steps_per_block);
 
 /* pool = f^0(rho, u = 0) for every instance; rho is the packed density array
  * (device, plan dtype).  Asynchronous on stream. */

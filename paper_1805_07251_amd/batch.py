@@ -57,6 +57,11 @@ class Batch:
     def set_launch(self, threads=256, blocks=0):
         V.check(V.lib().vdwlb_batch_set_launch(self.handle, int(threads), int(blocks)), "vdwlb_batch_set_launch")
 
+    def set_blocking(self, steps_per_block: int):
+        """Run in blocks of this many steps held in LDS (2, 4, 8), or step by
+        step (0)."""
+        V.check(V.lib().vdwlb_batch_set_blocking(self.handle, int(steps_per_block)), "vdwlb_batch_set_blocking")
+
     def pack(self, arrays) -> torch.Tensor:
         flat = np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in arrays])
         return torch.as_tensor(flat, dtype=self.torch_dtype).to(self.device)

@@ -121,6 +121,204 @@ struct Instance {
     Coeffs<C> k;
 };
 
+// Offsets of the pulled sources f_i(u - v_i) of site (u, y) in an LDS state
+// buffer of NY rows of W columns (the caller keeps u - 1 and u + 1 inside the
+// buffer; rows wrap).  The velocity order of pull_offsets.
+template <int NY, int W>
+__device__ __forceinline__ void lds_pull_offsets(int u, int y, int (&o)[Q]) {
+    const int ym = y == 0 ? NY - 1 : y - 1, yp = y == NY - 1 ? 0 : y + 1;
+    const int r0 = y * W, rm = ym * W, rp = yp * W;
+    o[0] = r0 + u;
+    o[1] = r0 + u - 1;
+    o[2] = rm + u;
+    o[3] = r0 + u + 1;
+    o[4] = rp + u;
+    o[5] = rm + u - 1;
+    o[6] = rm + u + 1;
+    o[7] = rp + u + 1;
+    o[8] = rp + u - 1;
+}
+
+// The nine pulled C-vectors of a site from an LDS state buffer with PLANE
+// sites per velocity plane.
+template <typename T, int C, int PLANE>
+__device__ __forceinline__ void pull_lds(const T* f, const int (&o)[Q], T (&p)[C][Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T v[C];
+        load_site<T, C>(f + i * PLANE * C, o[i], v);
+#pragma unroll
+        for (int c = 0; c < C; ++c) p[c][i] = v[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Temporal blocking of the batched D2Q9 sweep (lattices of height NY): a
+// workgroup loads a strip of TX columns and 3K columns on either side (every
+// row) into LDS once, advances it K steps there, and stores the TX interior
+// columns of the last step.  Each step's valid region shrinks by the 3
+// columns one step reaches (the pull, radius 1, after the radius-2 density
+// stencil of the potential gradient), so the halo is exactly used up.  Per K
+// steps HBM sees one read of (TX + 6K)/TX of the state and one write.  Each
+// thread owns one site of the W x NY block for all steps and keeps its pulled
+// populations and moments in registers across the barriers; every read of a
+// step's input happens before its first barrier, so the new state is written
+// over the old in place (one state buffer).  Every site goes through the
+// plain sweep's arithmetic (the same functions and stencil expressions), so
+// results are bit-identical to it.
+template <typename T, int C, int TX, int NY, int K>
+struct BlockLds {
+    static constexpr int W = TX + 6 * K;  // columns held
+    static constexpr int RY = NY + 2;     // padded rows of the density and potential arrays
+    static constexpr int PLANE = NY * W;  // sites of the block
+    static constexpr int NT = (PLANE + 63) / 64 * 64;  // one thread per site, whole wavefronts
+    static constexpr int STATE = Q * PLANE * C;        // elements of the state buffer
+    static constexpr int FIELD = C * RY * W;           // elements of the density or the potential array
+    static constexpr size_t bytes = (size_t)(STATE + 2 * FIELD) * sizeof(T);
+};
+
+// Number of steps of block b when nsteps steps run as nblocks blocks.
+__device__ __forceinline__ int block_steps(int nsteps, int nblocks, int b) {
+    return nsteps / nblocks + (b < nsteps % nblocks ? 1 : 0);
+}
+
+template <typename T, int C, int TX, int NY, int K, bool TAU1, typename R>
+__device__ __forceinline__ void block_strip(const T* __restrict__ src, T* __restrict__ dst, const Geometry& g,
+                                            const Coeffs<C, R>& k, int x0, int kk, int t0, T* s_f, T* s_rho,
+                                            T* s_phi, int* s_bad) {
+    using L = BlockLds<T, C, TX, NY, K>;
+    constexpr int W = L::W;
+    const int m = threadIdx.x;
+    const bool mine = m < L::PLANE;  // this thread's site (u, y) of the block
+    const int y = m / W, u = m - y * W;
+    // the block as it is in HBM: this site's nine C-vectors, loads first
+    {
+        T v[Q][C];
+        if (mine) {
+            const int x = wrapc(x0 - 3 * K + u, g.nx, 1);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) load_site<T, C>(plane_base<T, C>(src, i, g.plane), y * g.nx + x, v[i]);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) store_site<T, C, false>(s_f + i * L::PLANE * C, m, v[i]);
+        }
+    }
+    __syncthreads();
+    for (int j = 1; j <= kk; ++j) {
+        const int off = 3 * (K - kk + j);  // step j's output columns are [off, W - off)
+        T p[C][Q], rho[C], jx[C], jy[C];
+        // pull and densities on the output columns and a ring of 2
+        const bool in_r = mine && u >= off - 2 && u < W - off + 2;
+        if (in_r) {
+            int o[Q];
+            lds_pull_offsets<NY, W>(u, y, o);
+            pull_lds<T, C, L::PLANE>(s_f, o, p);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                rho[c] = density<T>(p[c]);
+                momentum<T>(p[c], jx[c], jy[c]);
+                put_wrapped<T, NY, W>(s_rho + c * L::RY * W, y + 1, u, rho[c]);
+            }
+        }
+        __syncthreads();
+        // potentials on the output columns and a ring of 1
+        if (mine && u >= off - 1 && u < W - off + 1) {
+            T r[C], l[C], ph[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                r[c] = s_rho[c * L::RY * W + (y + 1) * W + u];
+                l[c] = lap9s<T, W>(s_rho + c * L::RY * W, u, y + 1);
+            }
+            if (!potential<T, C>(r, l, k, ph)) atomicMin(s_bad, t0 + j);
+#pragma unroll
+            for (int c = 0; c < C; ++c) put_wrapped<T, NY, W>(s_phi + c * L::RY * W, y + 1, u, ph[c]);
+        }
+        __syncthreads();
+        // forces, friction and collision on the output columns, written over
+        // the old state (read in full before the first barrier); the last
+        // step stores the interior columns to HBM
+        if (mine && u >= off && u < W - off) {
+            T gx[C], gy[C], lap[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                T px, py, rx, ry;
+                grad9s<T, W>(s_phi + c * L::RY * W, u, y + 1, px, py);
+                grad9s<T, W>(s_rho + c * L::RY * W, u, y + 1, rx, ry);
+                lap[c] = lap9s<T, W>(s_rho + c * L::RY * W, u, y + 1);
+                gx[c] = -rho[c] * px;
+                gy[c] = -rho[c] * py;
+                if (k.force == 0) {
+                    gx[c] += T(THETA) * rx;
+                    gy[c] += T(THETA) * ry;
+                }
+            }
+            if (j < kk) {
+                collide_store<T, C, false, TAU1>(p, rho, jx, jy, gx, gy, lap, k, s_f, L::PLANE, m);
+            } else {
+                const int x = x0 + u - 3 * K;
+                if (x < g.nx)
+                    collide_store<T, C, false, TAU1>(p, rho, jx, jy, gx, gy, lap, k, dst, g.plane, y * g.nx + x);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The persistent batched sweep with temporal blocking: instances from the
+// largest-first queue; each instance runs its steps as nblocks blocks of at
+// most K steps (the block count has the parity of nsteps, so the result lands
+// in the buffer a step-by-step run would leave it in), every block strip by
+// strip.  An instance that becomes unphysical stops at the end of the block
+// in which it did; its status word records the first unphysical step.
+template <typename T, int C, int TX, int NY, int K, int TAUS>
+__global__ void __launch_bounds__((BlockLds<T, C, TX, NY, K>::NT)) k_batch_tb(
+    const Instance<C>* __restrict__ inst, const int* __restrict__ order, int n, T* poolA, T* poolB, int nsteps,
+    int nblocks, int* counter, int* __restrict__ status) {
+    using L = BlockLds<T, C, TX, NY, K>;
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    T* s_f = reinterpret_cast<T*>(s_raw);
+    T* s_rho = s_f + L::STATE;
+    T* s_phi = s_rho + L::FIELD;
+    __shared__ int s_job, s_bad;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_job = atomicAdd(counter, 1);
+            s_bad = 0x7fffffff;
+        }
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        if (job >= n) return;  // uniform: every wave exits, the queue is drained
+        const int id = __builtin_amdgcn_readfirstlane(order[job]);
+        const Instance<C>& I = inst[id];
+        const Geometry g = I.g;
+        T* A = poolA + I.offset;
+        T* B = poolB + I.offset;
+        const bool tau1 = TAUS == 1 || (TAUS == 0 && I.k.omega == 1.0);
+        int fail = 0, t0 = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            const int kk = block_steps(nsteps, nblocks, b);
+            const T* src = (b & 1) ? B : A;
+            T* dst = (b & 1) ? A : B;
+            for (int x0 = 0; x0 < g.nx; x0 += TX) {
+                if constexpr (TAUS == 1)
+                    block_strip<T, C, TX, NY, K, true>(src, dst, g, I.k, x0, kk, t0, s_f, s_rho, s_phi, &s_bad);
+                else if constexpr (TAUS == 2)
+                    block_strip<T, C, TX, NY, K, false>(src, dst, g, I.k, x0, kk, t0, s_f, s_rho, s_phi, &s_bad);
+                else if (tau1)
+                    block_strip<T, C, TX, NY, K, true>(src, dst, g, I.k, x0, kk, t0, s_f, s_rho, s_phi, &s_bad);
+                else
+                    block_strip<T, C, TX, NY, K, false>(src, dst, g, I.k, x0, kk, t0, s_f, s_rho, s_phi, &s_bad);
+            }
+            t0 += kk;
+            if (s_bad != 0x7fffffff) {  // read after block_strip's closing barrier: uniform
+                fail = s_bad;
+                break;
+            }
+        }
+        if (threadIdx.x == 0) status[id] = fail;
+        __syncthreads();
+    }
+}
+
 // Friction and D1Q3 collision of one site, the new populations written to
 // the LDS state [i][c][x] (same arithmetic as collide_store1).
 template <typename T, int C, bool TAU1, typename R>
@@ -429,6 +627,9 @@ struct vdwlb_batch {
     int* d_counter = nullptr;
     int threads = 256;  // workgroup size of the persistent kernel
     int blocks = 0;     // resident workgroups (0: fill the device)
+    int tb_k = 0;       // D2Q9: steps per temporal block (0: the step-by-step kernel)
+    size_t tb_lds = 0;  // dynamic LDS bytes of the blocked kernel
+    int tb_per = 1;     // resident workgroups of the blocked kernel per CU
     hipGraphExec_t graph = nullptr;
     const void *gA = nullptr, *gB = nullptr;
     int64_t gsteps = -1;
@@ -453,6 +654,83 @@ hipError_t launch_batch_shape(vdwlb_batch& b, void* A, void* B, int nsteps, int 
         hipLaunchKernelGGL((k_batch<T, C, TX, NY, 0>), dim3(blocks), dim3(TX * NY), 0, s, inst, b.d_order, b.n, (T*)A,
                            (T*)B, nsteps, b.d_counter, b.d_status);
     return hipGetLastError();
+}
+
+// Strip width of the blocked kernel for K steps per block: the block, strip
+// plus halo, is W = TX + 6K = 64 columns of 4 rows, one thread per site (256
+// threads; about 37-49 KB of LDS at C = 2 in FP64, so three or four
+// workgroups share a CU).
+template <int K>
+struct TbShape {
+    static constexpr int TX = 64 - 6 * K;
+};
+
+// Number of blocks of at most K steps for nsteps steps, with the parity of
+// nsteps (the result then lands in the buffer a step-by-step run leaves it in).
+int tb_blocks(int nsteps, int K) {
+    if (nsteps <= 0) return 0;
+    int nb = (nsteps + K - 1) / K;
+    if ((nb ^ nsteps) & 1) ++nb;
+    return nb;
+}
+
+template <typename T, int C, int K, int TAUS>
+hipError_t launch_tb_k(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, int what) {
+    using S = TbShape<K>;
+    using LB = BlockLds<T, C, S::TX, 4, K>;
+    auto kern = k_batch_tb<T, C, S::TX, 4, K, TAUS>;
+    const size_t lds = LB::bytes;
+    if (what == 1) {  // LDS attribute and resident workgroups per CU, outside any stream capture
+        b.tb_lds = lds;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int per = 0;
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, LB::NT, lds);
+        if (e == hipSuccess) b.tb_per = std::max(1, per);
+        return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(LB::NT), lds, s, (const Instance<C>*)b.d_inst, b.d_order, b.n, (T*)A,
+                       (T*)B, nsteps, tb_blocks(nsteps, K), b.d_counter, b.d_status);
+    return hipGetLastError();
+}
+
+// what: 0 launch, 1 set the LDS attribute of every collision variant and
+// record the resident workgroups per CU.
+template <typename T, int C, int K>
+hipError_t launch_tb_t(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, int what) {
+    if (what == 1) {
+        hipError_t e = launch_tb_k<T, C, K, 0>(b, A, B, nsteps, blocks, s, 1);
+        if (e == hipSuccess) e = launch_tb_k<T, C, K, 1>(b, A, B, nsteps, blocks, s, 1);
+        if (e == hipSuccess) e = launch_tb_k<T, C, K, 2>(b, A, B, nsteps, blocks, s, 1);
+        return e;
+    }
+    if (b.taus == 1) return launch_tb_k<T, C, K, 1>(b, A, B, nsteps, blocks, s, what);
+    if (b.taus == 2) return launch_tb_k<T, C, K, 2>(b, A, B, nsteps, blocks, s, what);
+    return launch_tb_k<T, C, K, 0>(b, A, B, nsteps, blocks, s, what);
+}
+
+template <typename T, int C>
+hipError_t launch_tb_c(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, int what) {
+    switch (b.tb_k) {
+        case 2: return launch_tb_t<T, C, 2>(b, A, B, nsteps, blocks, s, what);
+        case 3: return launch_tb_t<T, C, 3>(b, A, B, nsteps, blocks, s, what);
+        case 4: return launch_tb_t<T, C, 4>(b, A, B, nsteps, blocks, s, what);
+        case 5: return launch_tb_t<T, C, 5>(b, A, B, nsteps, blocks, s, what);
+        case 6: return launch_tb_t<T, C, 6>(b, A, B, nsteps, blocks, s, what);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// The blocked kernel exists for C = 1, 2 in either precision and height 4.
+hipError_t launch_tb(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks, hipStream_t s, int what) {
+    if (b.dim != 2 || b.ny != 4) return hipErrorInvalidValue;
+    if (b.dtype == VDWLB_F64)
+        return b.C == 1 ? launch_tb_c<double, 1>(b, A, B, nsteps, blocks, s, what)
+               : b.C == 2 ? launch_tb_c<double, 2>(b, A, B, nsteps, blocks, s, what)
+                          : hipErrorInvalidValue;
+    return b.C == 1 ? launch_tb_c<float, 1>(b, A, B, nsteps, blocks, s, what)
+           : b.C == 2 ? launch_tb_c<float, 2>(b, A, B, nsteps, blocks, s, what)
+                      : hipErrorInvalidValue;
 }
 
 template <typename T, int C, int THREADS>
@@ -524,6 +802,7 @@ hipError_t launch_batch(vdwlb_batch& b, void* A, void* B, int nsteps, int blocks
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b.d_counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (b.tb_k > 0) return launch_tb(b, A, B, nsteps, blocks, s, 0);
     return b.dtype == VDWLB_F64 ? launch_batch_t<double>(b, A, B, nsteps, blocks, s)
                                 : launch_batch_t<float>(b, A, B, nsteps, blocks, s);
 }
@@ -596,6 +875,7 @@ int device_blocks(const vdwlb_batch& b) {
         const size_t per = std::max<size_t>(1, std::min<size_t>(8, lds_cu / std::max<size_t>(b.lds1 + 64, 1)));
         return cus * (int)per;
     }
+    if (b.tb_k > 0) return cus * b.tb_per;  // as many as fit a CU's LDS and waves
     const int per_cu = (b.threads == 1024 && b.ny >= 4) ? 1 : 4;
     return cus * per_cu;
 }
@@ -704,6 +984,15 @@ vdwlb_status vdwlb_batch_create(int32_t n, const vdwlb_desc* descs, vdwlb_batch*
         vdwlb_batch_destroy(b);
         return bfail(e, "batch device buffers");
     }
+    // D2Q9 batches of height 4 run with temporal blocking by default (3 steps
+    // per block: the fastest measured on the 1024-lattice workload)
+    if (dim == 2 && ny == 4 && C <= 2) {
+        const vdwlb_status st = vdwlb_batch_set_blocking(b, 3);
+        if (st != VDWLB_OK && st != VDWLB_E_UNSUPPORTED) {
+            vdwlb_batch_destroy(b);
+            return st;
+        }
+    }
     *out = b;
     return VDWLB_OK;
 }
@@ -737,6 +1026,31 @@ vdwlb_status vdwlb_batch_set_launch(vdwlb_batch* b, int32_t threads, int32_t blo
     if (threads != b->threads || blocks != b->blocks) release_batch_graph(*b);
     b->threads = threads;
     b->blocks = blocks;
+    return VDWLB_OK;
+}
+
+vdwlb_status vdwlb_batch_set_blocking(vdwlb_batch* b, int32_t steps_per_block) {
+    if (!b || steps_per_block < 0 || steps_per_block == 1 || steps_per_block > 6) return VDWLB_E_INVALID_ARG;
+    if (steps_per_block == b->tb_k) return VDWLB_OK;
+    if (steps_per_block > 0) {
+        if (b->dim != 2 || b->ny != 4 || b->C > 2) return VDWLB_E_UNSUPPORTED;
+        const int keep = b->tb_k;
+        b->tb_k = steps_per_block;
+        size_t lds_wg = 64 * 1024;
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lds_wg = prop.sharedMemPerBlock;
+        hipError_t e = launch_tb(*b, nullptr, nullptr, 0, 0, nullptr, 1);
+        if (e == hipSuccess && b->tb_lds > lds_wg) e = hipErrorInvalidValue;
+        if (e != hipSuccess) {
+            b->tb_k = keep;
+            (void)hipGetLastError();
+            return b->tb_lds > lds_wg ? VDWLB_E_UNSUPPORTED : bfail(e, "batch blocking");
+        }
+    }
+    release_batch_graph(*b);
+    b->tb_k = steps_per_block;
     return VDWLB_OK;
 }
 

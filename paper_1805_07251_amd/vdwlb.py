@@ -62,6 +62,7 @@ _SIGS = {
     "vdwlb_batch_offset": (ctypes.c_int64, [_VP, ctypes.c_int32]),
     "vdwlb_batch_density_offset": (ctypes.c_int64, [_VP, ctypes.c_int32]),
     "vdwlb_batch_set_launch": (ctypes.c_int32, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "vdwlb_batch_set_blocking": (ctypes.c_int32, [_VP, ctypes.c_int32]),
     "vdwlb_batch_init": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
     "vdwlb_batch_density": (ctypes.c_int32, [_VP, _VP, _VP, _VP]),
     "vdwlb_batch_run": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_int32)]),
