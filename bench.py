@@ -460,10 +460,11 @@ def verification_leg(n=16, steps=50000):
     a, b = I.binary_mixture(0.4, 0.4, 1.0, 1.0, 0.5)
     NA, NB = phase.composition_grid(b, 64)
     t0 = time.perf_counter()
-    r = VV.run_three_phase(1 / 3, a, b, NA, NB, steps=steps, setup=VV.SlabSetup(kappa=0.1))
+    r = VV.run_three_phase(1 / 3, a, b, NA, NB, steps=steps, setup=VV.SlabSetup(kappa=0.1, L=512))
     secs = time.perf_counter() - t0
     ok = r.status == 0
-    out["baseline_three_phase"] = {"grid": 64, "kappa": 0.1, "runs": int(len(r.status)),
+    out["baseline_three_phase"] = {"grid": 64, "kappa": 0.1, "line": 512, "min_domain": 24,
+                                   "runs": int(len(r.status)),
                                    "unphysical": int((~ok).sum()), "steps": steps, "seconds": secs,
                                    "deviation_median": float(np.median(r.deviation[ok])),
                                    "deviation_p90": float(np.percentile(r.deviation[ok], 90)),

@@ -85,21 +85,25 @@ def test_interface_width_iteration(mods):
 def test_three_phase_region_runs(mods):
     """The three-phase region of the baseline mixture (Fig. graphBaselineCase,
     the paper's largest set of runs): every three-phase point of a 64 x 64
-    grid with domains of at least 12 sites is run as gas | A-rich | gas |
-    B-rich on 256 sites with kappa = 0.1.  All runs stay physical and their
-    bulk states reach the one three-phase state (Gibbs phase rule): after
-    50,000 steps the median distance is below 1e-4 (measured 1.4e-5; the
-    paper reports ~1e-3 at the binodal intersections) and every run is
-    within 3e-2; 200,000 steps do not move the median up."""
+    grid whose smallest domain has at least 24 sites is run as gas | A-rich |
+    gas | B-rich on 512 sites with kappa = 0.1.  All runs stay physical and
+    their bulk states reach the one three-phase state (Gibbs phase rule):
+    after 50,000 steps every run is within 1e-3 of it, the paper's accuracy at
+    the binodal intersections (measured: median 2.3e-7, 90th percentile
+    1.9e-5, largest 2.3e-4); 200,000 steps do not move the median up.  With
+    domains down to 12 sites on 256-site lines, a few points at the edges of
+    the region left their bulk windows inside the interfaces' tails (90th
+    percentile 5.4e-3, largest 1.9e-2)."""
     phase, V = mods
     a, b = T.two_component_params(0.4, 0.4, 1.0, 0.5)
     NA, NB = phase.composition_grid(b, 64)
-    setup = V.SlabSetup(kappa=0.1)
+    setup = V.SlabSetup(kappa=0.1, L=512)
     r1 = V.run_three_phase(KT, a, b, NA, NB, steps=50000, setup=setup)
     assert len(r1.status) >= 20 and np.all(r1.status == 0)
     # every point ran from the same three phases (the unique three-phase state)
     assert np.ptp(r1.predicted, axis=0).max() < 1e-10
-    assert np.median(r1.deviation) < 1e-4 and r1.deviation.max() < 3e-2
+    assert np.median(r1.deviation) < 1e-5
+    assert np.percentile(r1.deviation, 90) < 1e-3 and r1.deviation.max() < 1e-3
     r2 = V.run_three_phase(KT, a, b, NA, NB, steps=200000, setup=setup)
     assert np.all(r2.status == 0)
     assert np.median(r2.deviation) <= np.median(r1.deviation) * 1.01 + 1e-12
