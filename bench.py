@@ -367,12 +367,18 @@ def adjoint_leg(seed):
     from paper_1805_07251_amd.lattice import Lattice
 
     w, tgt = I.adjoint_case(seed)
+    # the plain forward on the autotuner's schedule; the adjoint's forward and
+    # recompute run the same schedule
+    lat = Lattice.from_workload(w)
+    lat.init(w.rho)
+    sched = lat.autotune()
     theta = A.theta_from_params(w.kT, w.a, w.b, I.KAPPA)
-    spec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam)
+    spec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam,
+                  schedule=sched)
     rho0 = torch.as_tensor(w.rho, device="cuda")
     tg = torch.as_tensor(tgt, device="cuda")
-    # warm-up (allocator, code objects); each call below builds its own plan and
-    # captures its graphs, as a caller of the autograd function does
+    # warm-up (allocator, code objects); each call below builds its own plan,
+    # as a caller of the autograd function does
     A.run_and_grad(theta, rho0, spec, lambda r: ((r[0] - tg) ** 2).sum())
     torch.cuda.synchronize()
     fwd, bwd = [], []
@@ -389,7 +395,6 @@ def adjoint_leg(seed):
         fwd.append(t1 - t0)
         bwd.append(t2 - t1)
     # the plain forward for the same 2000 steps (its step graph captured beforehand)
-    lat = Lattice.from_workload(w)
     lat.init(w.rho)
     lat.run(64)
     torch.cuda.synchronize()
@@ -406,6 +411,7 @@ def adjoint_leg(seed):
     return {
         "workload": "256x256 D2Q9, C=2, FP64, 2000 steps, checkpoints every 100",
         "timing": "best of 3 of each",
+        "schedule": sched,
         "forward_ms": f * 1e3,
         "backward_ms": b * 1e3,
         "plain_forward_ms": pf * 1e3,

@@ -395,6 +395,19 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* plan, const void* f_ckpt, int32_t
 vdwlb_status vdwlb_adjoint_segment_noalloc(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* fbar_io,
                                            double* pbar_accum, void* stream);
 
+/* Graph replay of the adjoint's parts (vdwlb_adjoint_segment,
+ * vdwlb_adjoint_recompute, vdwlb_adjoint_reverse) for this plan: enable = 1
+ * replays each part from a hipGraph captured on its first use and bound to
+ * its step count and buffers (the workspace; for the reverse sweep also
+ * fbar_io and pbar_accum), enable = 0 (the default) launches the kernels one
+ * by one.  Replay pays only when a plan reverses with the same buffers many
+ * times: each kernel runs for microseconds, so eager launches keep the device
+ * busy, and a capture costs more host time than it saves.  A plan keeps up
+ * to six graphs and makes the device idle before it drops the oldest.
+ * Results are the same bit for bit either way.  VDWLB_E_INVALID_ARG for a
+ * NULL plan or enable other than 0 or 1. */
+vdwlb_status vdwlb_set_adjoint_graphs(vdwlb_plan* plan, int32_t enable);
+
 /* The two halves of vdwlb_adjoint_segment, for callers that overlap the
  * forward recompute of one segment with the reverse sweep of the next one on
  * a second stream (the recompute depends only on its checkpoint), each half
@@ -407,12 +420,10 @@ vdwlb_status vdwlb_adjoint_segment_noalloc(vdwlb_plan* plan, const void* f_ckpt,
  * the two, by stream or event); it replaces fbar_io and adds to pbar_accum
  * exactly as vdwlb_adjoint_segment does, which is the recompute followed by
  * the reverse sweep on one stream.  A workspace must not be recomputed into
- * while a reverse sweep that reads it may still run.  Each half is replayed
- * from a hipGraph captured on first use and bound to its step count and
- * buffers (the workspace; for the reverse sweep also fbar_io and pbar_accum);
- * a plan keeps up to six such graphs, and makes the device idle before it
- * drops the oldest.  Asynchronous on stream; arguments and errors as for
- * vdwlb_adjoint_segment. */
+ * while a reverse sweep that reads it may still run.  Each half launches its
+ * kernels one by one on stream, unless graph replay is switched on for the
+ * plan (vdwlb_set_adjoint_graphs).  Asynchronous on stream; arguments and
+ * errors as for vdwlb_adjoint_segment. */
 vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* workspace,
                                      void* stream);
 vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* plan, int32_t nsteps, void* fbar_io, void* workspace,

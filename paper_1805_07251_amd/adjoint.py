@@ -57,7 +57,11 @@ class Spec:
     gamma_mu: float = 1.0
     lam: np.ndarray | None = None
     force: int = V.FORCE_LOG
-    schedule: int | None = None  # sweep schedule of the forward and recompute (default: the plan's)
+    # sweep schedule of the forward and the recompute: "auto" (the autotuner's
+    # choice, found once per lattice shape and kept), None (the plan's
+    # default) or a schedule index; every schedule gives the same results
+    schedule: int | str | None = "auto"
+    graphs: bool = False  # replay the backward's recompute / reverse parts from captured hipGraphs
 
 
 class VdwLBFunction(torch.autograd.Function):
@@ -66,14 +70,15 @@ class VdwLBFunction(torch.autograd.Function):
         th = theta.detach().cpu().numpy().astype(np.float64)
         kT, a, b, kappa = params_from_theta(th, spec.C, spec.k_hat)
         plan = Plan(spec.nx, spec.ny, kT, a, b, kappa, spec.tau, spec.gamma_mu, spec.lam, "f64", spec.force)
-        if spec.schedule is not None:
-            V.check(V.lib().vdwlb_set_schedule(plan.handle, int(spec.schedule)), "vdwlb_set_schedule")
+        if spec.graphs:
+            V.check(V.lib().vdwlb_set_adjoint_graphs(plan.handle, 1), "vdwlb_set_adjoint_graphs")
         dev = rho0.device
         n = plan.state_elems
         bufs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
         r0 = rho0.detach().to(torch.float64).contiguous()
         s = _stream_ptr()
         V.check(V.lib().vdwlb_init(plan.handle, bufs[0].data_ptr(), r0.data_ptr(), None, s), "vdwlb_init")
+        _apply_schedule(plan, spec, bufs, s)
         ckpts, segs = [], []
         cur, done = 0, 0
         which = ctypes.c_int32()
@@ -122,6 +127,30 @@ class VdwLBFunction(torch.autograd.Function):
         dkappa = sum(g[1 + na + C + q] * k_hat[c, d] for q, (c, d) in enumerate(pairs))
         grad = np.concatenate([g[:1 + na + C], [dkappa]])
         return torch.as_tensor(grad, dtype=ctx.theta_dtype, device=ctx.theta_device), None, None
+
+
+_TUNED = {}
+
+
+def _apply_schedule(plan, spec: Spec, bufs, stream) -> None:
+    """Set the sweep schedule of the forward and the recompute: an explicit
+    index, the plan's default (None), or the autotuner's choice for this
+    lattice shape, component count and kernel variant, timed on the first
+    call (on the initial state in bufs[0], overwriting only bufs[1]) and
+    kept for later calls."""
+    if spec.schedule is None:
+        return
+    if spec.schedule != "auto":
+        V.check(V.lib().vdwlb_set_schedule(plan.handle, int(spec.schedule)), "vdwlb_set_schedule")
+        return
+    key = (bufs[0].device.index, spec.nx, spec.ny, spec.C, spec.tau == 1.0, int(spec.force))
+    if key not in _TUNED:
+        k = ctypes.c_int32()
+        V.check(V.lib().vdwlb_autotune(plan.handle, bufs[0].data_ptr(), bufs[1].data_ptr(), stream, ctypes.byref(k)),
+                "vdwlb_autotune")
+        _TUNED[key] = k.value
+    else:
+        V.check(V.lib().vdwlb_set_schedule(plan.handle, _TUNED[key]), "vdwlb_set_schedule")
 
 
 _AUX_STREAMS = {}

@@ -41,6 +41,7 @@ namespace adj {
 
 constexpr int TX = 32, TY = 8;  // tile of the reverse-sweep kernels (A, B, fused)
 constexpr int BLK = 256;        // workgroup of the per-site kernels (C, moments adjoint, reduction)
+constexpr int NTF = 2 * TX * TY;  // workgroup of the fused kernel: two threads per tile site
 static_assert(TX * TY == BLK, "a tile is one workgroup of BLK threads");
 
 // number of parameters in the cotangent vector:
@@ -322,6 +323,39 @@ __device__ __forceinline__ void reduce_partial(double (&s_red)[NP][NT], const do
     }
 }
 
+// The same reduction of NT values per entry (already in s_red) by one
+// wavefront, lane l = threadIdx.x - first: the LDS levels h = NT/2, ..., 64
+// of reduce_partial leave at position l the sum of s_red[.][l + 64 j] over j
+// combined in the same pairs, which a lane forms directly from the 64-strided
+// values; the shuffle levels follow unchanged.  Needs no barrier, so one
+// otherwise idle wavefront can reduce while the others go on.
+template <int NP, int NT>
+__device__ __forceinline__ void reduce_partial_wave(const double (&s_red)[NP][NT], int first,
+                                                    double* __restrict__ out) {
+    static_assert(NT % 64 == 0 && NT >= 64, "whole wavefronts");
+    constexpr int J = NT / 64;
+    const int l = (int)threadIdx.x - first;
+    double v[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        double x[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) x[j] = s_red[q][l + 64 * j];
+#pragma unroll
+        for (int h = J / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int j = 0; j < h; ++j) x[j] += x[j + h];
+        v[q] = x[0];
+    }
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v[q] += __shfl_down(v[q], h, 64);
+    if (l == 0)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) out[q] = v[q];
+}
+
 // Tile origin of workgroup b (row-major tiles).
 __device__ __forceinline__ void tile_origin(const Geometry& g, int& x0, int& y0) {
     const int tiles_x = (g.nx + TX - 1) / TX;
@@ -483,14 +517,21 @@ __global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Field
 // kernel B's order.  Then C's gather at each site gives the cotangent of
 // step t's new state (written to fbo) and, with DO_A, A of step t runs on it
 // at once.  Results equal the sequence A, B, C bit for bit.
+//
+// Two threads per tile site (NTF = 2 TX TY, two wavefronts per SIMD): thread
+// t < TX TY owns tile site t (B there, the gather and A), thread TX TY + r
+// owns radius-2 ring site r (B there); A's potential on the tile plus a
+// radius-1 ring is spread over the threads from the top down, so that no
+// thread evaluates more than two sites between the barriers.
 template <int C, bool DO_A>
-__global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ fbn, double* __restrict__ fbo,
-                                                    Geometry g, Coeffs<C> k, Fields Fn, Fields F,
-                                                    double* __restrict__ partial) {
+__global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn, double* __restrict__ fbo,
+                                                 Geometry g, Coeffs<C> k, Fields Fn, Fields F,
+                                                 double* __restrict__ partial) {
     constexpr int NT = TX * TY, NP = n_params(C);
     constexpr int X3 = TX + 6, Y3 = TY + 6, X2 = TX + 4, Y2 = TY + 4, X1 = TX + 2, Y1 = TY + 2;
     constexpr int RING2 = X2 * Y2 - TX * TY;
-    static_assert(RING2 <= NT, "one radius-2 ring site per thread");
+    static_assert(RING2 <= NTF - NT, "one radius-2 ring site per thread of the upper half");
+    static_assert(X1 * Y1 <= NTF, "one potential site per thread");
     __shared__ double s_av[2 * C][X3 * Y3];
     __shared__ double s_bv[2 * C][X3 * Y3];
     __shared__ double s_rn[C][X3 * Y3];  // densities of step t + 1
@@ -505,28 +546,30 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     const int64_t N = (int64_t)g.nx * g.ny;
     int x0, y0;
     tile_origin(g, x0, y0);
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int t = threadIdx.x;
+    const bool own = t < NT;
+    const int lx = t % TX, ly = (t % NT) / TX;
     const int x = x0 + lx, y = y0 + ly;
-    const bool inside = x < g.nx && y < g.ny;
+    const bool inside = own && x < g.nx && y < g.ny;
     const int xw = wrapg(x, g.nx, g.wrap_general), yw = wrapg(y, g.ny, g.wrap_general);
     const int s = yw * g.nx + xw;  // this thread's tile site (wrapped when outside the lattice)
-    int ring_ex = 0, ring_ey = 0;
-    const bool has_ring = (int)threadIdx.x < RING2;
-    if (has_ring) ring_coords<TX, TY>(threadIdx.x, ring_ex, ring_ey);
-    const int ring_s = wrapg(y0 - 2 + ring_ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + ring_ex, g.nx, g.wrap_general);
+    // the site of the radius-2 grid this thread evaluates B at
+    int bx = lx + 2, by = ly + 2;
+    const bool has_b = own || t - NT < RING2;
+    if (!own && has_b) ring_coords<TX, TY>(t - NT, bx, by);
+    const int b_s = wrapg(y0 - 2 + by, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 2 + bx, g.nx, g.wrap_general);
 
     // Every global read first, into registers, so that their latencies
-    // overlap (at one wavefront per SIMD each wait would otherwise be
-    // exposed): step t + 1's fields around the tile, step t's densities
-    // around it, the Laplacian cotangent of the sites this thread evaluates B
-    // at, the cotangents the gather takes from the neighbours and step t's
-    // moments at the own site; then the LDS stores.
-    constexpr int N3 = (X3 * Y3 + NT - 1) / NT, N1 = (X1 * Y1 + NT - 1) / NT;
-    constexpr int N2 = (X2 * Y2 + NT - 1) / NT;
+    // overlap: step t + 1's fields around the tile, step t's densities around
+    // it, the Laplacian cotangent of the site this thread evaluates B at, the
+    // cotangents the gather takes from the neighbours and step t's moments at
+    // the own site; then the LDS stores.
+    constexpr int N3 = (X3 * Y3 + NTF - 1) / NTF, N1 = (X1 * Y1 + NTF - 1) / NTF;
+    constexpr int N2 = (X2 * Y2 + NTF - 1) / NTF;
     double v3[N3][5 * C], v1[N1][3 * C], v2[N2][C];
 #pragma unroll
     for (int it = 0; it < N3; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = t + it * NTF;
         if (e < X3 * Y3) {
             const int ey = e / X3, ex = e - ey * X3;
             const int q = wrapg(y0 - 3 + ey, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 3 + ex, g.nx, g.wrap_general);
@@ -542,7 +585,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     }
 #pragma unroll
     for (int it = 0; it < N1; ++it) {
-        const int m = threadIdx.x + it * NT;
+        const int m = t + it * NTF;
         if (m < X1 * Y1) {
             const int my = m / X1, mx = m - my * X1;
             const int q = wrapg(y0 - 1 + my, g.ny, g.wrap_general) * g.nx + wrapg(x0 - 1 + mx, g.nx, g.wrap_general);
@@ -557,7 +600,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     if constexpr (DO_A) {
 #pragma unroll
         for (int it = 0; it < N2; ++it) {
-            const int e = threadIdx.x + it * NT;
+            const int e = t + it * NTF;
             if (e < X2 * Y2) {
                 const int ey = e / X2, ex = e - ey * X2;
                 const int q =
@@ -567,26 +610,23 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
             }
         }
     }
-    double lb_own[C], lb_ring[C], fb_nb[C][Q], rho[C], jx[C], jy[C];
+    double lb_b[C], fb_nb[C][Q], rho[C], jx[C], jy[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        lb_own[c] = Fn.lb[c * N + s];
-        lb_ring[c] = has_ring ? Fn.lb[c * N + ring_s] : 0.0;
-    }
+    for (int c = 0; c < C; ++c) lb_b[c] = has_b ? Fn.lb[c * N + b_s] : 0.0;
     if (inside) {
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+        for (int i = 0; i < Q; ++i) {
+            const int src = wrapg(y + VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x + VX[i], g.nx, g.wrap_general);
+            double v[C];
+            load_site<double, C>(fbn + (int64_t)i * g.plane * C, src, v);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const int src =
-                    wrapg(y + VY[i], g.ny, g.wrap_general) * g.nx + wrapg(x + VX[i], g.nx, g.wrap_general);
-                fb_nb[c][i] = fbn[((int64_t)i * g.plane + src) * C + c];
-            }
+            for (int c = 0; c < C; ++c) fb_nb[c][i] = v[c];
+        }
         if constexpr (DO_A) load_moments<C>(F, N, s, rho, jx, jy);
     }
 #pragma unroll
     for (int it = 0; it < N3; ++it) {
-        const int e = threadIdx.x + it * NT;
+        const int e = t + it * NTF;
         if (e < X3 * Y3)
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -599,7 +639,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     }
 #pragma unroll
     for (int it = 0; it < N1; ++it) {
-        const int m = threadIdx.x + it * NT;
+        const int m = t + it * NTF;
         if (m < X1 * Y1)
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -611,7 +651,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     if constexpr (DO_A) {
 #pragma unroll
         for (int it = 0; it < N2; ++it) {
-            const int e = threadIdx.x + it * NT;
+            const int e = t + it * NTF;
             if (e < X2 * Y2)
 #pragma unroll
                 for (int c = 0; c < C; ++c) s_rho[c][e] = v2[it][c];
@@ -619,59 +659,81 @@ __global__ void __launch_bounds__(TX* TY) k_adj_bca(const double* __restrict__ f
     }
     __syncthreads();
 
-    // A's potential of step t, and B of step t + 1 on the tile (own site, with
-    // the parameter partial when it lies in the lattice) and on the radius-2
-    // ring around it
-    if constexpr (DO_A) eval_potential<C>(k, s_rho, s_phi);
+    // A's potential of step t (site NTF - 1 - t of the radius-1 grid), and B
+    // of step t + 1 at this thread's site of the radius-2 grid (with the
+    // parameter partial when it is an own site in the lattice)
+    if constexpr (DO_A) {
+        constexpr int EX = TX + 4, MX = TX + 2;
+        const int m = NTF - 1 - t;
+        if (m < X1 * Y1) {
+            const int my = m / MX, mx = m - my * MX;
+            double r[C], l[C], ph[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                r[c] = s_rho[c][(my + 1) * EX + mx + 1];
+                l[c] = lap9s<double, EX>(s_rho[c], mx + 1, my + 1);
+            }
+            potential<double, C>(r, l, k, ph);
+#pragma unroll
+            for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
+        }
+    }
     double acc[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-    auto b_site = [&](int ex, int ey, const double (&lb)[C], bool own) {  // ex, ey: position in the radius-2 grid
-        const int e3 = (ey + 1) * X3 + ex + 1, e2 = ey * X2 + ex;
+    if (has_b) {
+        const int e3 = (by + 1) * X3 + bx + 1, e2 = by * X2 + bx;
         double rn[C], L[C], phib[C], dbv[C], rbb[C], lbt[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             rn[c] = s_rn[c][e3];
-            L[c] = lap9s<double, X3>(s_rn[c], ex + 1, ey + 1);
-            phib[c] = div9s<X3>(s_av[2 * c], s_av[2 * c + 1], ex + 1, ey + 1);
-            dbv[c] = k.force == 0 ? div9s<X3>(s_bv[2 * c], s_bv[2 * c + 1], ex + 1, ey + 1) : 0.0;
+            L[c] = lap9s<double, X3>(s_rn[c], bx + 1, by + 1);
+            phib[c] = div9s<X3>(s_av[2 * c], s_av[2 * c + 1], bx + 1, by + 1);
+            dbv[c] = k.force == 0 ? div9s<X3>(s_bv[2 * c], s_bv[2 * c + 1], bx + 1, by + 1) : 0.0;
         }
-        if (own)
-            adjoint_potential<C, true>(rn, L, phib, dbv, lb, k, rbb, lbt, acc);
+        if (inside)
+            adjoint_potential<C, true>(rn, L, phib, dbv, lb_b, k, rbb, lbt, acc);
         else
-            adjoint_potential<C, false>(rn, L, phib, dbv, lb, k, rbb, lbt, nullptr);
+            adjoint_potential<C, false>(rn, L, phib, dbv, lb_b, k, rbb, lbt, nullptr);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             s_rbb[c][e2] = rbb[c];
             s_lbt[c][e2] = lbt[c];
         }
-    };
-    b_site(lx + 2, ly + 2, lb_own, inside);
-    if (has_ring) b_site(ring_ex, ring_ey, lb_ring, false);
+    }
+    if (own)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) s_red[q][t] = acc[q];
     __syncthreads();
     // C of step t + 1: total density cotangent on the tile and a radius-1 ring
-    for (int m = threadIdx.x; m < X1 * Y1; m += NT) {
-        const int my = m / X1, mx = m - my * X1;
+    if (t < X1 * Y1) {
+        const int my = t / X1, mx = t - my * X1;
         const int e2 = (my + 1) * X2 + mx + 1;
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            s_rb[c][m] = (s_rb[c][m] + s_rbb[c][e2]) + lap9s<double, X2>(s_lbt[c], mx + 1, my + 1);
+            s_rb[c][t] = (s_rb[c][t] + s_rbb[c][e2]) + lap9s<double, X2>(s_lbt[c], mx + 1, my + 1);
     }
-    reduce_partial<NP, NT>(s_red, acc, partial + (int64_t)blockIdx.x * NP);  // its first barrier orders s_rb
+    __syncthreads();
+    // the tile's parameter partial, by the last wavefront (idle from here on)
+    static_assert(X1 * Y1 <= NTF - 64 && RING2 <= NTF - 64 - NT, "the last wavefront has no site of its own");
+    if (t >= NTF - 64) {
+        reduce_partial_wave<NP, NT>(s_red, NTF - 64, partial + (int64_t)blockIdx.x * NP);
+        return;
+    }
     if (!inside) return;
     const double omega = k.omega;
     // the un-streamed cotangent at this site: step t's incoming cotangent
     double fin[C][Q];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
+    for (int i = 0; i < Q; ++i) {
+        const int q = (ly + 1 + VY[i]) * X1 + (lx + 1 + VX[i]);
+        double v[C];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int q = (ly + 1 + VY[i]) * X1 + (lx + 1 + VX[i]);
-            const double pb =
-                (1.0 - omega) * fb_nb[c][i] + s_rb[c][q] + s_jx[c][q] * VX[i] + s_jy[c][q] * VY[i];
-            fin[c][i] = pb;
-            fbo[((int64_t)i * g.plane + s) * C + c] = pb;
+        for (int c = 0; c < C; ++c) {
+            v[c] = (1.0 - omega) * fb_nb[c][i] + s_rb[c][q] + s_jx[c][q] * VX[i] + s_jy[c][q] * VY[i];
+            fin[c][i] = v[c];
         }
+        store_site<double, C, false>(fbo + (int64_t)i * g.plane * C, s, v);
     }
     if constexpr (DO_A) {
         double dpx[C], dpy[C], rx[C], ry[C];
@@ -853,13 +915,13 @@ struct StepKernels {
     }
     // B and C of step t + 1 fused with A of step t
     void bca(int t, const double* fbn, double* fbo) {
-        hipLaunchKernelGGL((adj::k_adj_bca<C, true>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
+        hipLaunchKernelGGL((adj::k_adj_bca<C, true>), dim3(L.tiles), dim3(adj::NTF), 0, s, fbn, fbo, g, k,
                            fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t), partial_row(t + 1));
     }
     // B and C of step 0
     void bc(const double* fbn, double* fbo) {
         const adj::Fields F0 = fields_at(p, L, ws, 0);
-        hipLaunchKernelGGL((adj::k_adj_bca<C, false>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, fbo, g, k,
+        hipLaunchKernelGGL((adj::k_adj_bca<C, false>), dim3(L.tiles), dim3(adj::NTF), 0, s, fbn, fbo, g, k,
                            F0, F0, partial_row(0));
     }
 };
@@ -921,13 +983,14 @@ hipError_t enqueue_reverse(const vdwlb_plan& p, const Layout& L, double* ws, int
     return e;
 }
 
-// Replays the captured graph of `key` (capturing it on first use) on stream s,
-// or launches eagerly when graphs are switched off.  Holds at most six graphs
-// per plan: the recompute and reverse graphs of two workspaces for the full
-// segment length and for a shorter last segment.
+// Launches the kernels of one part eagerly on stream s, or, when the plan asks
+// for graph replay, replays the captured graph of `key` (capturing it on
+// first use).  Holds at most six graphs per plan: the recompute and reverse
+// graphs of two workspaces for the full segment length and for a shorter
+// last segment.
 template <typename Enqueue>
 vdwlb_status run_part(vdwlb_plan& p, const AdjointGraph& key, hipStream_t s, Enqueue enqueue, const char* what) {
-    if (!graphs_enabled()) {
+    if (!p.adj_graphs || !graphs_enabled()) {
         const hipError_t e = enqueue(s);
         return e == hipSuccess ? VDWLB_OK : set_device_error(e, what);
     }
@@ -1077,6 +1140,12 @@ vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* p, int32_t nsteps, void* fbar_io,
             return enqueue_reverse(*p, L, ws, nsteps, (double*)fbar_io, pbar_accum, cs, key.fused);
         },
         "adjoint reverse");
+}
+
+vdwlb_status vdwlb_set_adjoint_graphs(vdwlb_plan* p, int32_t enable) {
+    if (!p || (enable != 0 && enable != 1)) return VDWLB_E_INVALID_ARG;
+    p->adj_graphs = enable == 1;
+    return VDWLB_OK;
 }
 
 vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io, void* workspace,

@@ -32,6 +32,7 @@ struct vdwlb_plan {
     const void* gA = nullptr;
     const void* gB = nullptr;
     hipStream_t capture_stream = nullptr;
+    bool adj_graphs = false;        // replay adjoint recompute / reverse parts from captured graphs
     std::vector<AdjointGraph> adj;  // captured recompute / reverse graphs of up to two workspaces
 };
 

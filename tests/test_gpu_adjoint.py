@@ -11,6 +11,8 @@ error.  Checks:
   - the benchmark's 256 x 256, 2000-step case against central finite
     differences of the GPU forward (h = 1e-6).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -249,10 +251,12 @@ def test_adjoint_case_forward_densities(gpu):
 
 
 def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
-    """The backward pass replays each checkpoint segment from a captured
-    hipGraph (the checkpoint copy stays eager between replays); the gradient
-    must equal the eager launch sequence bit for bit, over repeated
-    backward passes."""
+    """With graph replay switched on for the plan (vdwlb_set_adjoint_graphs)
+    the backward pass replays each checkpoint segment's parts from captured
+    hipGraphs (the checkpoint copy stays eager between replays); the gradient
+    must equal the eager launch sequence (the default, and with every graph
+    switched off by VDWLB_NO_GRAPH) bit for bit, over repeated backward
+    passes."""
     adjoint, _, _ = gpu
     P = mixture(2)
     k_hat = P["kappa"] / 0.1
@@ -263,11 +267,13 @@ def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
                          device="cuda")
     theta = adjoint.theta_from_params(P["kT"], P["a"], P["b"], 0.1)
     spec = adjoint.Spec(nx, ny, 2, k_hat, nsteps, ckpt=20, tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"])
+    gspec = dataclasses.replace(spec, graphs=True)
     loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
     r0 = torch.as_tensor(rho0, device="cuda")
-    graphed = [adjoint.run_and_grad(theta, r0, spec, loss_fn) for _ in range(2)]
-    monkeypatch.setenv("VDWLB_NO_GRAPH", "1")
+    graphed = [adjoint.run_and_grad(theta, r0, gspec, loss_fn) for _ in range(2)]
     eager = adjoint.run_and_grad(theta, r0, spec, loss_fn)
+    monkeypatch.setenv("VDWLB_NO_GRAPH", "1")
+    graphed.append(adjoint.run_and_grad(theta, r0, gspec, loss_fn))
     for loss, grad in graphed:
         assert loss == eager[0]
         assert np.array_equal(grad, eager[1])
@@ -331,8 +337,7 @@ def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
     serial = adjoint.run_and_grad(theta, r0, spec, loss_fn)
     monkeypatch.delenv("VDWLB_ADJ_SERIAL")
     runs = [adjoint.run_and_grad(theta, r0, spec, loss_fn) for _ in range(2)]
-    monkeypatch.setenv("VDWLB_NO_GRAPH", "1")
-    runs.append(adjoint.run_and_grad(theta, r0, spec, loss_fn))
+    runs += [adjoint.run_and_grad(theta, r0, dataclasses.replace(spec, graphs=True), loss_fn) for _ in range(2)]
     for loss, grad in runs:
         assert loss == serial[0]
         assert np.array_equal(grad, serial[1])
@@ -342,8 +347,9 @@ def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
 def test_row_schedules_equal_default(gpu, tau):
     """The recompute inside the backward pass runs the plan's sweep schedule
     in its moment-writing form; the schedules with several rows of sites per
-    thread (tau = 1 keeps only the rows' moments, tau != 1 pulls again) must
-    give the default schedule's loss and gradient bit for bit."""
+    thread (tau = 1 keeps only the rows' moments, tau != 1 pulls again) and
+    the autotuner's choice must give the default schedule's loss and gradient
+    bit for bit."""
     adjoint, _, _ = gpu
     P = mixture(2, tau=tau)
     k_hat = P["kappa"] / 0.1
@@ -356,7 +362,7 @@ def test_row_schedules_equal_default(gpu, tau):
     loss_fn = lambda r: ((r[0] - tg) ** 2).sum()
     r0 = torch.as_tensor(rho0, device="cuda")
     out = []
-    for sched in (None, 14, 15, 36):
+    for sched in (None, "auto", 14, 15, 36):
         spec = adjoint.Spec(nx, ny, 2, k_hat, nsteps, ckpt=10, tau=P["tau"], gamma_mu=P["gamma_mu"], lam=P["lam"],
                             schedule=sched)
         out.append(adjoint.run_and_grad(theta, r0, spec, loss_fn))
