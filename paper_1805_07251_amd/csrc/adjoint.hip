@@ -52,16 +52,17 @@ __host__ __device__ constexpr int pair_index(int C, int c, int d) {
     return (c <= d) ? c * C - c * (c - 1) / 2 + (d - c) : d * C - d * (d - 1) / 2 + (c - d);
 }
 
-// Per-step fields of the reverse sweep.  av, bv, lb, rhob_loc and jb exist
+// Per-step fields of the reverse sweep.  g0b, lb, rhob_loc and jb exist
 // twice, by step parity: the fused kernel of step t reads step t + 1's values
-// around its tile while it writes step t's.
+// around its tile while it writes step t's.  Kernel B needs the vectors
+// av = rho G0b and (log forcing) bv = G0b around each site; only G0b is kept,
+// and av is formed where it is read, as the same single product.
 struct Fields {
     const double* rho;  // [C][N] moments of the forward step
     const double* mom;  // [C][2][N]
     double* rhob_loc;   // [C][N]
     double* jb;         // [C][2][N]
-    double* av;         // [C][2][N]
-    double* bv;         // [C][2][N]
+    double* g0b;        // [C][2][N] cotangent of the mean-field force G0
     double* lb;         // [C][N] Laplacian cotangent from the collision
     double* rhob_b;     // [C][N]
     double* lb_tot;     // [C][N]
@@ -86,6 +87,23 @@ __device__ __forceinline__ double div9(const double* vx, const double* vy, const
     const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
     const double ax = 4.0 * (vx[r0 + xp] - vx[r0 + xm]) + ((vx[rp + xp] - vx[rp + xm]) + (vx[rm + xp] - vx[rm + xm]));
     const double ay = 4.0 * (vy[rp + x] - vy[rm + x]) + ((vy[rp + xp] + vy[rp + xm]) - (vy[rm + xm] + vy[rm + xp]));
+    return (ax + ay) * (1.0 / 12.0);
+}
+
+// The divergence of av = r V on global fields, each product formed on its
+// own (as where av is staged) and combined as in div9.
+__device__ __forceinline__ double div9r(const double* r, const double* vx, const double* vy, const Geometry& g, int x,
+                                        int y) {
+    const int xm = wrapg(x - 1, g.nx, g.wrap_general), xp = wrapg(x + 1, g.nx, g.wrap_general), ym = wrapg(y - 1, g.ny, g.wrap_general), yp = wrapg(y + 1, g.ny, g.wrap_general);
+    const int r0 = y * g.nx, rm = ym * g.nx, rp = yp * g.nx;
+    auto px = [&](int i) { const double p = r[i] * vx[i]; return p; };
+    auto py = [&](int i) { const double p = r[i] * vy[i]; return p; };
+    const double a0p = px(r0 + xp), a0m = px(r0 + xm), app = px(rp + xp), apm = px(rp + xm), amp = px(rm + xp),
+                 amm = px(rm + xm);
+    const double bp0 = py(rp + x), bm0 = py(rm + x), bpp = py(rp + xp), bpm = py(rp + xm), bmm = py(rm + xm),
+                 bmp = py(rm + xp);
+    const double ax = 4.0 * (a0p - a0m) + ((app - apm) + (amp - amm));
+    const double ay = 4.0 * (bp0 - bm0) + ((bpp + bpm) - (bmm + bmp));
     return (ax + ay) * (1.0 / 12.0);
 }
 
@@ -118,8 +136,8 @@ template <int C>
 __device__ __forceinline__ void adjoint_local(const double (&fin)[C][Q], const double (&rho)[C], const double (&jx)[C],
                                               const double (&jy)[C], const double (&dpx)[C], const double (&dpy)[C],
                                               const double (&rx)[C], const double (&ry)[C], const Coeffs<C>& k,
-                                              double (&rb)[C], double (&jbx)[C], double (&jby)[C], double (&avx)[C],
-                                              double (&avy)[C], double (&bvx)[C], double (&bvy)[C], double (&lb)[C]) {
+                                              double (&rb)[C], double (&jbx)[C], double (&jby)[C], double (&gbx_out)[C],
+                                              double (&gby_out)[C], double (&lb)[C]) {
     const double omega = k.omega, cG = k.cG, cL = k.cL;
     double g0x[C], g0y[C];
 #pragma unroll
@@ -217,10 +235,8 @@ __device__ __forceinline__ void adjoint_local(const double (&fin)[C][Q], const d
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         rb[c] -= g0bx[c] * dpx[c] + g0by[c] * dpy[c];
-        avx[c] = rho[c] * g0bx[c];
-        avy[c] = rho[c] * g0by[c];
-        bvx[c] = k.force == 0 ? g0bx[c] : 0.0;
-        bvy[c] = k.force == 0 ? g0by[c] : 0.0;
+        gbx_out[c] = g0bx[c];
+        gby_out[c] = g0by[c];
     }
 }
 
@@ -366,18 +382,15 @@ __device__ __forceinline__ void tile_origin(const Geometry& g, int& x0, int& y0)
 // Writes the local adjoint of one site into the step's fields.
 template <int C>
 __device__ __forceinline__ void store_local(const Fields& F, int64_t N, int s, const double (&rb)[C],
-                                            const double (&jbx)[C], const double (&jby)[C], const double (&avx)[C],
-                                            const double (&avy)[C], const double (&bvx)[C], const double (&bvy)[C],
-                                            const double (&lb)[C]) {
+                                            const double (&jbx)[C], const double (&jby)[C], const double (&gbx)[C],
+                                            const double (&gby)[C], const double (&lb)[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         F.rhob_loc[c * N + s] = rb[c];
         F.jb[(2 * c) * N + s] = jbx[c];
         F.jb[(2 * c + 1) * N + s] = jby[c];
-        F.av[(2 * c) * N + s] = avx[c];
-        F.av[(2 * c + 1) * N + s] = avy[c];
-        F.bv[(2 * c) * N + s] = bvx[c];
-        F.bv[(2 * c + 1) * N + s] = bvy[c];
+        F.g0b[(2 * c) * N + s] = gbx[c];
+        F.g0b[(2 * c + 1) * N + s] = gby[c];
         F.lb[c * N + s] = lb[c];
     }
 }
@@ -468,9 +481,9 @@ __global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn
     double rho[C], jx[C], jy[C], dpx[C], dpy[C], rx[C], ry[C];
     load_moments<C>(F, N, s, rho, jx, jy);
     local_stencils<C>(lx, ly, s_rho, s_phi, dpx, dpy, rx, ry);
-    double rb[C], jbx[C], jby[C], avx[C], avy[C], bvx[C], bvy[C], lb[C];
-    adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, avx, avy, bvx, bvy, lb);
-    store_local<C>(F, N, s, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+    double rb[C], jbx[C], jby[C], gbx[C], gby[C], lb[C];
+    adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, gbx, gby, lb);
+    store_local<C>(F, N, s, rb, jbx, jby, gbx, gby, lb);
 }
 
 // Kernel B: potential adjoint and parameter cotangents of each site of a tile
@@ -493,8 +506,8 @@ __global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Field
         for (int c = 0; c < C; ++c) {
             rho[c] = F.rho[c * N + s];
             L[c] = lapg(F.rho + c * N, g, x, y);
-            phib[c] = div9(F.av + (2 * c) * N, F.av + (2 * c + 1) * N, g, x, y);
-            dbv[c] = k.force == 0 ? div9(F.bv + (2 * c) * N, F.bv + (2 * c + 1) * N, g, x, y) : 0.0;
+            phib[c] = div9r(F.rho + c * N, F.g0b + (2 * c) * N, F.g0b + (2 * c + 1) * N, g, x, y);
+            dbv[c] = k.force == 0 ? div9(F.g0b + (2 * c) * N, F.g0b + (2 * c + 1) * N, g, x, y) : 0.0;
             lb[c] = F.lb[c * N + s];
         }
         adjoint_potential<C, true>(rho, L, phib, dbv, lb, k, rbb, lbt, acc);
@@ -566,7 +579,7 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
     // the own site; then the LDS stores.
     constexpr int N3 = (X3 * Y3 + NTF - 1) / NTF, N1 = (X1 * Y1 + NTF - 1) / NTF;
     constexpr int N2 = (X2 * Y2 + NTF - 1) / NTF;
-    double v3[N3][5 * C], v1[N1][3 * C], v2[N2][C];
+    double v3[N3][3 * C], v1[N1][3 * C], v2[N2][C];
 #pragma unroll
     for (int it = 0; it < N3; ++it) {
         const int e = t + it * NTF;
@@ -576,10 +589,8 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 v3[it][c] = Fn.rho[c * N + q];
-                v3[it][C + 2 * c] = Fn.av[(2 * c) * N + q];
-                v3[it][C + 2 * c + 1] = Fn.av[(2 * c + 1) * N + q];
-                v3[it][3 * C + 2 * c] = k.force == 0 ? Fn.bv[(2 * c) * N + q] : 0.0;
-                v3[it][3 * C + 2 * c + 1] = k.force == 0 ? Fn.bv[(2 * c + 1) * N + q] : 0.0;
+                v3[it][C + 2 * c] = Fn.g0b[(2 * c) * N + q];
+                v3[it][C + 2 * c + 1] = Fn.g0b[(2 * c + 1) * N + q];
             }
         }
     }
@@ -630,11 +641,13 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
         if (e < X3 * Y3)
 #pragma unroll
             for (int c = 0; c < C; ++c) {
+                const double ax = v3[it][c] * v3[it][C + 2 * c];
+                const double ay = v3[it][c] * v3[it][C + 2 * c + 1];
                 s_rn[c][e] = v3[it][c];
-                s_av[2 * c][e] = v3[it][C + 2 * c];
-                s_av[2 * c + 1][e] = v3[it][C + 2 * c + 1];
-                s_bv[2 * c][e] = v3[it][3 * C + 2 * c];
-                s_bv[2 * c + 1][e] = v3[it][3 * C + 2 * c + 1];
+                s_av[2 * c][e] = ax;
+                s_av[2 * c + 1][e] = ay;
+                s_bv[2 * c][e] = k.force == 0 ? v3[it][C + 2 * c] : 0.0;
+                s_bv[2 * c + 1][e] = k.force == 0 ? v3[it][C + 2 * c + 1] : 0.0;
             }
     }
 #pragma unroll
@@ -738,9 +751,9 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
     if constexpr (DO_A) {
         double dpx[C], dpy[C], rx[C], ry[C];
         local_stencils<C>(lx, ly, s_rho, s_phi, dpx, dpy, rx, ry);
-        double rb[C], jbx[C], jby[C], avx[C], avy[C], bvx[C], bvy[C], lb[C];
-        adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, avx, avy, bvx, bvy, lb);
-        store_local<C>(F, N, s, rb, jbx, jby, avx, avy, bvx, bvy, lb);
+        double rb[C], jbx[C], jby[C], gbx[C], gby[C], lb[C];
+        adjoint_local<C>(fin, rho, jx, jy, dpx, dpy, rx, ry, k, rb, jbx, jby, gbx, gby, lb);
+        store_local<C>(F, N, s, rb, jbx, jby, gbx, gby, lb);
     }
 }
 
@@ -862,7 +875,7 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
     L.moms = o;
     o += (int64_t)nsteps * 3 * p.C * L.N;
     L.fields = o;
-    o += 18 * (int64_t)p.C * L.N;
+    o += 14 * (int64_t)p.C * L.N;
     L.partial = o;  // one partial vector per tile and per step
     o += (int64_t)nsteps * L.tiles * L.np;
     L.total = o;
@@ -870,7 +883,7 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
 }
 
 // Fields of step t: the moments of its forward recompute, and the adjoint
-// fields, those read around a tile by the next kernel (rhob_loc, jb, av, bv,
+// fields, those read around a tile by the next kernel (rhob_loc, jb, g0b,
 // lb) by step parity.
 adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
     adj::Fields F;
@@ -878,14 +891,13 @@ adj::Fields fields_at(const vdwlb_plan& p, const Layout& L, double* ws, int t) {
     const double* mom0 = ws + L.moms + (int64_t)t * 3 * CN;
     F.rho = mom0;
     F.mom = mom0 + CN;
-    double* f = ws + L.fields + ((t & 1) ? 8 * CN : 0);  // per parity: rhob_loc C, jb 2C, av 2C, bv 2C, lb C
+    double* f = ws + L.fields + ((t & 1) ? 6 * CN : 0);  // per parity: rhob_loc C, jb 2C, g0b 2C, lb C
     F.rhob_loc = f;
     F.jb = f + CN;
-    F.av = f + 3 * CN;
-    F.bv = f + 5 * CN;
-    F.lb = f + 7 * CN;
-    F.rhob_b = ws + L.fields + 16 * CN;
-    F.lb_tot = ws + L.fields + 17 * CN;
+    F.g0b = f + 3 * CN;
+    F.lb = f + 5 * CN;
+    F.rhob_b = ws + L.fields + 12 * CN;
+    F.lb_tot = ws + L.fields + 13 * CN;
     return F;
 }
 
