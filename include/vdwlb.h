@@ -350,8 +350,8 @@ int32_t vdwlb_adjoint_param_count(const vdwlb_plan* plan);
 
 /* Bytes of device workspace vdwlb_adjoint_segment needs for nsteps steps:
  * three state buffers, the densities and momenta of every step of the
- * segment (3 C nx ny doubles per step), per-site intermediate fields and the
- * per-workgroup parameter partial sums of every step. */
+ * segment (3 C nx ny doubles per step), per-site intermediate fields and one
+ * running parameter partial sum per tile. */
 size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* plan, int32_t nsteps);
 
 /* Cotangent of a state given cotangents of its read-out densities rho_bar

@@ -308,12 +308,14 @@ __device__ __forceinline__ void adjoint_potential(const double (&rho)[C], const 
 
 // Tree reduction of the per-thread parameter cotangents of a workgroup (NT
 // threads, fixed order: at each level h = NT/2, ..., 1 thread t < h adds
-// thread t + h's value) into one partial vector.  The levels that cross
-// wavefronts go through LDS; the last six run within wavefront 0 by shuffles,
-// with the same pairs in the same order.  Every thread must call it.
+// thread t + h's value) into the tile's running partial vector out: with
+// accumulate, out + sum, else the sum alone (the segment's first reversed
+// step).  The levels that cross wavefronts go through LDS; the last six run
+// within wavefront 0 by shuffles, with the same pairs in the same order.
+// Every thread must call it.
 template <int NP, int NT>
 __device__ __forceinline__ void reduce_partial(double (&s_red)[NP][NT], const double (&acc)[NP],
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, int accumulate) {
     static_assert(NT % 64 == 0 && NT >= 64, "whole wavefronts");
     const int t = threadIdx.x;
 #pragma unroll
@@ -335,7 +337,7 @@ __device__ __forceinline__ void reduce_partial(double (&s_red)[NP][NT], const do
             for (int q = 0; q < NP; ++q) v[q] += __shfl_down(v[q], h, 64);
         if (t == 0)
 #pragma unroll
-            for (int q = 0; q < NP; ++q) out[q] = v[q];
+            for (int q = 0; q < NP; ++q) out[q] = accumulate ? out[q] + v[q] : v[q];
     }
 }
 
@@ -344,10 +346,11 @@ __device__ __forceinline__ void reduce_partial(double (&s_red)[NP][NT], const do
 // of reduce_partial leave at position l the sum of s_red[.][l + 64 j] over j
 // combined in the same pairs, which a lane forms directly from the 64-strided
 // values; the shuffle levels follow unchanged.  Needs no barrier, so one
-// otherwise idle wavefront can reduce while the others go on.
+// otherwise idle wavefront can reduce while the others go on.  prev: the
+// running partial read earlier (used with accumulate, as in reduce_partial).
 template <int NP, int NT>
-__device__ __forceinline__ void reduce_partial_wave(const double (&s_red)[NP][NT], int first,
-                                                    double* __restrict__ out) {
+__device__ __forceinline__ void reduce_partial_wave(const double (&s_red)[NP][NT], int first, const double (&prev)[NP],
+                                                    double* __restrict__ out, int accumulate) {
     static_assert(NT % 64 == 0 && NT >= 64, "whole wavefronts");
     constexpr int J = NT / 64;
     const int l = (int)threadIdx.x - first;
@@ -369,7 +372,7 @@ __device__ __forceinline__ void reduce_partial_wave(const double (&s_red)[NP][NT
         for (int q = 0; q < NP; ++q) v[q] += __shfl_down(v[q], h, 64);
     if (l == 0)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) out[q] = v[q];
+        for (int q = 0; q < NP; ++q) out[q] = accumulate ? prev[q] + v[q] : v[q];
 }
 
 // Tile origin of workgroup b (row-major tiles).
@@ -489,7 +492,8 @@ __global__ void __launch_bounds__(TX* TY) k_adj_a(const double* __restrict__ fbn
 // Kernel B: potential adjoint and parameter cotangents of each site of a tile
 // (one partial vector per tile, reduced in a fixed order).
 template <int C>
-__global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Fields F, double* __restrict__ partial) {
+__global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Fields F, double* __restrict__ partial,
+                                                  int accumulate) {
     constexpr int NP = n_params(C), NT = TX * TY;
     __shared__ double s_red[NP][NT];
     const int64_t N = (int64_t)g.nx * g.ny;
@@ -517,7 +521,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Field
             F.rhob_b[c * N + s] = rbb[c];
         }
     }
-    reduce_partial<NP, NT>(s_red, acc, partial + (int64_t)blockIdx.x * NP);
+    reduce_partial<NP, NT>(s_red, acc, partial + (int64_t)blockIdx.x * NP, accumulate);
 }
 
 // The fused kernel of one reversed step: B and C of step t + 1 and (with
@@ -539,7 +543,7 @@ __global__ void __launch_bounds__(TX* TY) k_adj_b(Geometry g, Coeffs<C> k, Field
 template <int C, bool DO_A>
 __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn, double* __restrict__ fbo,
                                                  Geometry g, Coeffs<C> k, Fields Fn, Fields F,
-                                                 double* __restrict__ partial) {
+                                                 double* __restrict__ partial, int accumulate) {
     constexpr int NT = TX * TY, NP = n_params(C);
     constexpr int X3 = TX + 6, Y3 = TY + 6, X2 = TX + 4, Y2 = TY + 4, X1 = TX + 2, Y1 = TY + 2;
     constexpr int RING2 = X2 * Y2 - TX * TY;
@@ -621,7 +625,10 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
             }
         }
     }
-    double lb_b[C], fb_nb[C][Q], rho[C], jx[C], jy[C];
+    double lb_b[C], fb_nb[C][Q], rho[C], jx[C], jy[C], prev[NP];
+    // the tile's running partial, for the wavefront that adds to it
+#pragma unroll
+    for (int q = 0; q < NP; ++q) prev[q] = accumulate && t >= NTF - 64 ? partial[(int64_t)blockIdx.x * NP + q] : 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) lb_b[c] = has_b ? Fn.lb[c * N + b_s] : 0.0;
     if (inside) {
@@ -730,7 +737,7 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
     // the tile's parameter partial, by the last wavefront (idle from here on)
     static_assert(X1 * Y1 <= NTF - 64 && RING2 <= NTF - 64 - NT, "the last wavefront has no site of its own");
     if (t >= NTF - 64) {
-        reduce_partial_wave<NP, NT>(s_red, NTF - 64, partial + (int64_t)blockIdx.x * NP);
+        reduce_partial_wave<NP, NT>(s_red, NTF - 64, prev, partial + (int64_t)blockIdx.x * NP, accumulate);
         return;
     }
     if (!inside) return;
@@ -757,7 +764,7 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
     }
 }
 
-// Fixed-order reduction of the per-workgroup partials of a whole segment
+// Fixed-order reduction of the tiles' running partials of a whole segment
 // (n vectors of np entries) into pbar (+=): workgroup q sums entry q.
 __global__ void __launch_bounds__(BLK) k_adj_reduce(const double* __restrict__ partial, int n, int np,
                                                      double* __restrict__ pbar) {
@@ -876,8 +883,8 @@ Layout layout(const vdwlb_plan& p, int nsteps) {
     o += (int64_t)nsteps * 3 * p.C * L.N;
     L.fields = o;
     o += 14 * (int64_t)p.C * L.N;
-    L.partial = o;  // one partial vector per tile and per step
-    o += (int64_t)nsteps * L.tiles * L.np;
+    L.partial = o;  // one running partial vector per tile
+    o += (int64_t)L.tiles * L.np;
     L.total = o;
     return L;
 }
@@ -911,14 +918,15 @@ struct StepKernels {
     Coeffs<C> k;
     StepKernels(const vdwlb_plan& p_, const Layout& L_, double* ws_, hipStream_t s_)
         : p(p_), L(L_), ws(ws_), s(s_), g(adjoint_geometry(p_)), k(make_coeffs<C>(p_)) {}
-    double* partial_row(int t) const { return ws + L.partial + (int64_t)t * L.tiles * L.np; }
+    double* partial() const { return ws + L.partial; }
     void a(int t, const double* fbn) {
         hipLaunchKernelGGL((adj::k_adj_a<C>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, fbn, g, k,
                            fields_at(p, L, ws, t));
     }
-    void b(int t) {
+    // accumulate: the tiles' running partials already hold a later step's
+    void b(int t, int accumulate) {
         hipLaunchKernelGGL((adj::k_adj_b<C>), dim3(L.tiles), dim3(adj::TX * adj::TY), 0, s, g, k,
-                           fields_at(p, L, ws, t), partial_row(t));
+                           fields_at(p, L, ws, t), partial(), accumulate);
     }
     void c(int t, const double* fbn, double* fbo) {
         const int nb = (int)((L.N + adj::BLK - 1) / adj::BLK);
@@ -926,15 +934,15 @@ struct StepKernels {
                            fields_at(p, L, ws, t));
     }
     // B and C of step t + 1 fused with A of step t
-    void bca(int t, const double* fbn, double* fbo) {
+    void bca(int t, const double* fbn, double* fbo, int accumulate) {
         hipLaunchKernelGGL((adj::k_adj_bca<C, true>), dim3(L.tiles), dim3(adj::NTF), 0, s, fbn, fbo, g, k,
-                           fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t), partial_row(t + 1));
+                           fields_at(p, L, ws, t + 1), fields_at(p, L, ws, t), partial(), accumulate);
     }
     // B and C of step 0
-    void bc(const double* fbn, double* fbo) {
+    void bc(const double* fbn, double* fbo, int accumulate) {
         const adj::Fields F0 = fields_at(p, L, ws, 0);
         hipLaunchKernelGGL((adj::k_adj_bca<C, false>), dim3(L.tiles), dim3(adj::NTF), 0, s, fbn, fbo, g, k,
-                           F0, F0, partial_row(0));
+                           F0, F0, partial(), accumulate);
     }
 };
 
@@ -954,14 +962,15 @@ hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int n
     if (!fused) {
         for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
             K.a(t, bufs[k & 1]);
-            K.b(t);
+            K.b(t, t < nsteps - 1);
             K.c(t, bufs[k & 1], bufs[(k + 1) & 1]);
         }
         return hipGetLastError();
     }
     K.a(nsteps - 1, bufs[0]);
-    for (int t = nsteps - 2, k = 1; t >= 0; --t, ++k) K.bca(t, bufs[(k - 1) & 1], bufs[k & 1]);
-    K.bc(bufs[(nsteps - 1) & 1], bufs[nsteps & 1]);
+    // the running partials start with the last step's (each kernel adds step t + 1's)
+    for (int t = nsteps - 2, k = 1; t >= 0; --t, ++k) K.bca(t, bufs[(k - 1) & 1], bufs[k & 1], t < nsteps - 2);
+    K.bc(bufs[(nsteps - 1) & 1], bufs[nsteps & 1], nsteps > 1);
     return hipGetLastError();
 }
 
@@ -987,7 +996,7 @@ hipError_t enqueue_reverse(const vdwlb_plan& p, const Layout& L, double* ws, int
                             : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
     if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
         hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
-                           nsteps * L.tiles, L.np, pbar);
+                           L.tiles, L.np, pbar);
         e = hipGetLastError();
     }
     if (e == hipSuccess && (nsteps & 1))
