@@ -426,6 +426,18 @@ vdwlb_status vdwlb_set_adjoint_graphs(vdwlb_plan* plan, int32_t enable);
  * errors as for vdwlb_adjoint_segment. */
 vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* plan, const void* f_ckpt, int32_t nsteps, void* workspace,
                                      void* stream);
+
+/* The forward of a segment that keeps what its reverse sweep needs, for the
+ * last segment of a checkpointed run, whose states the caller has just
+ * computed anyway: nsteps (>= 1) steps from f_in, the state after them
+ * written to f_out (f_out may be f_in), and the workspace left exactly as
+ * vdwlb_adjoint_recompute(plan, f_in, nsteps, workspace) leaves it, so that
+ * vdwlb_adjoint_reverse may follow with no recompute.  f_out equals
+ * vdwlb_step's result bit for bit.  Asynchronous on stream; arguments and
+ * errors as for vdwlb_adjoint_recompute (f_out checked like f_in, before
+ * anything is enqueued). */
+vdwlb_status vdwlb_adjoint_forward(vdwlb_plan* plan, const void* f_in, int32_t nsteps, void* f_out, void* workspace,
+                                   void* stream);
 vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* plan, int32_t nsteps, void* fbar_io, void* workspace,
                                    double* pbar_accum, void* stream);
 

@@ -1,7 +1,10 @@
 """Differentiation through many sweep steps: a torch.autograd.Function whose
 backward pass is the library's hand-written adjoint with segment
 checkpointing (the forward keeps the state every `ckpt` steps; the backward
-recomputes each segment from its checkpoint and reverses it).
+recomputes each segment from its checkpoint and reverses it).  The last
+segment is never recomputed: the forward runs it with
+vdwlb_adjoint_forward, which keeps its densities and momenta in a
+workspace that the backward reverses first.
 
 Parameters theta = [kT, a^{cd} (c <= d), b^c, kappa] with the gradient
 matrix kappa^{cd} = kappa * K_hat^{cd} (K_hat fixed), i.e. for two
@@ -79,24 +82,30 @@ class VdwLBFunction(torch.autograd.Function):
         s = _stream_ptr()
         V.check(V.lib().vdwlb_init(plan.handle, bufs[0].data_ptr(), r0.data_ptr(), None, s), "vdwlb_init")
         _apply_schedule(plan, spec, bufs, s)
-        ckpts, segs = [], []
-        cur, done = 0, 0
+        segs = [min(spec.ckpt, spec.nsteps - d) for d in range(0, spec.nsteps, spec.ckpt)]
+        ckpts = []  # the states the recomputed segments (all but the last) start from
+        cur = 0
         which = ctypes.c_int32()
-        while done < spec.nsteps:
-            m = min(spec.ckpt, spec.nsteps - done)
+        for m in segs[:-1]:
             ckpts.append(bufs[cur].clone())
-            segs.append(m)
             V.check(V.lib().vdwlb_step(plan.handle, bufs[cur].data_ptr(), bufs[1 - cur].data_ptr(), m, s,
                                        ctypes.byref(which)), "vdwlb_step")
             if which.value == 1:
                 cur = 1 - cur
-            done += m
+        # the last segment keeps what its reverse sweep needs
+        ws_last = torch.empty(int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, segs[-1])) // 8 + 1,
+                              dtype=torch.float64, device=dev)
+        V.check(V.lib().vdwlb_adjoint_forward(plan.handle, bufs[cur].data_ptr(), segs[-1], bufs[1 - cur].data_ptr(),
+                                              ws_last.data_ptr(), s), "vdwlb_adjoint_forward")
+        cur = 1 - cur
         C, ny, nx = spec.C, spec.ny, spec.nx
         rho = torch.empty((C, ny, nx), dtype=torch.float64, device=dev)
         mom = torch.empty((C, 2, ny, nx), dtype=torch.float64, device=dev)
         V.check(V.lib().vdwlb_moments(plan.handle, bufs[cur].data_ptr(), rho.data_ptr(), mom.data_ptr(), None, None,
                                       s), "vdwlb_moments")
-        ctx.plan, ctx.spec, ctx.ckpts, ctx.segs = plan, spec, ckpts, segs
+        ctx.plan, ctx.spec, ctx.ckpts, ctx.segs, ctx.ws_last = plan, spec, ckpts, segs, ws_last
+        ctx.forward_done = torch.cuda.Event()
+        ctx.forward_done.record(torch.cuda.current_stream(dev))
         ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
         return rho
 
@@ -111,14 +120,25 @@ class VdwLBFunction(torch.autograd.Function):
                 "vdwlb_moments_adjoint")
         npar = int(V.lib().vdwlb_adjoint_param_count(plan.handle))
         pbar = torch.zeros(npar, dtype=torch.float64, device=dev)
-        ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(ctx.segs)))
-        if len(ctx.segs) > 1 and os.environ.get("VDWLB_ADJ_SERIAL") != "1":
-            _reverse_overlapped(plan, ctx.ckpts, ctx.segs, fbar, pbar, ws_bytes, dev)
+        segs = ctx.segs
+        torch.cuda.current_stream(dev).wait_event(ctx.forward_done)  # the last segment's workspace
+
+        def reverse_last():  # the last segment first, from the forward's workspace
+            V.check(V.lib().vdwlb_adjoint_reverse(plan.handle, int(segs[-1]), fbar.data_ptr(),
+                                                  ctx.ws_last.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_reverse")
+
+        if len(segs) == 1:
+            reverse_last()
         else:
-            ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
-            for ck, m in zip(reversed(ctx.ckpts), reversed(ctx.segs)):
-                V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(),
-                                                      ws.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_segment")
+            ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(segs[:-1])))
+            if os.environ.get("VDWLB_ADJ_SERIAL") != "1":
+                _reverse_overlapped(plan, ctx.ckpts, segs[:-1], fbar, pbar, ws_bytes, dev, first=reverse_last)
+            else:
+                reverse_last()
+                ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
+                for ck, m in zip(reversed(ctx.ckpts), reversed(segs[:-1])):
+                    V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(),
+                                                          ws.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_segment")
         g = pbar.cpu().numpy()
         C = spec.C
         pairs = theta_layout(C)
@@ -166,12 +186,14 @@ def _aux_stream(dev):
     return _AUX_STREAMS[key]
 
 
-def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev):
+def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev, first=None):
     """Reverse the segments from the last to the first with the forward
     recompute of segment k - 1 on a second stream, into a second workspace,
-    while the reverse sweep of segment k runs on the current stream.  The
-    reverse sweeps run in the same order on one stream as the one-stream
-    loop, so the results are the same bit for bit."""
+    while the reverse sweep of segment k runs on the current stream.  first,
+    if given, enqueues a reverse sweep that precedes them on the current
+    stream (one that needs no recompute); the recompute of the last segment
+    here runs beside it.  The reverse sweeps run in the same order on one
+    stream as the one-stream loop, so the results are the same bit for bit."""
     lib = V.lib()
     main = torch.cuda.current_stream(dev)
     aux = _aux_stream(dev)
@@ -190,6 +212,8 @@ def _reverse_overlapped(plan, ckpts, segs, fbar, pbar, ws_bytes, dev):
         return ev
 
     ready = recompute(len(segs) - 1)
+    if first is not None:
+        first()
     for k in range(len(segs) - 1, -1, -1):
         nxt = recompute(k - 1) if k > 0 else None
         main.wait_event(ready)

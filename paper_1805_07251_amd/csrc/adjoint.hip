@@ -1141,6 +1141,22 @@ vdwlb_status vdwlb_adjoint_recompute(vdwlb_plan* p, const void* f_ckpt, int32_t 
         *p, key, s, [&](hipStream_t cs) { return enqueue_recompute(*p, L, ws, nsteps, cs); }, "adjoint recompute");
 }
 
+vdwlb_status vdwlb_adjoint_forward(vdwlb_plan* p, const void* f_in, int32_t nsteps, void* f_out, void* workspace,
+                                   void* stream) {
+    vdwlb_status st = check_adjoint(p, nsteps, workspace);
+    if (st != VDWLB_OK) return st;
+    if (!f_in || !f_out || !state_aligned(*p, f_in) || !state_aligned(*p, f_out)) return VDWLB_E_INVALID_ARG;
+    st = vdwlb_adjoint_recompute(p, f_in, nsteps, workspace, stream);
+    if (st != VDWLB_OK) return st;
+    // the recompute leaves step nsteps's state in the first buffer after an
+    // even number of steps, in the second after an odd number
+    const Layout L = layout(*p, nsteps);
+    const double* last = (const double*)workspace + ((nsteps & 1) ? L.f1 : L.f0);
+    const hipError_t e =
+        hipMemcpyAsync(f_out, last, (size_t)L.state * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? VDWLB_OK : set_device_error(e, "adjoint forward state copy");
+}
+
 vdwlb_status vdwlb_adjoint_reverse(vdwlb_plan* p, int32_t nsteps, void* fbar_io, void* workspace,
                                    double* pbar_accum, void* stream) {
     vdwlb_status st = check_adjoint(p, nsteps, workspace);

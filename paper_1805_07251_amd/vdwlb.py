@@ -75,6 +75,7 @@ _SIGS = {
     "vdwlb_adjoint_reverse": (ctypes.c_int32, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "vdwlb_adjoint_segment_noalloc": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     "vdwlb_set_adjoint_graphs": (ctypes.c_int32, [_VP, ctypes.c_int32]),
+    "vdwlb_adjoint_forward": (ctypes.c_int32, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     "vdwlb_pressure_tensor": (ctypes.c_int32, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "vdwlb_phase_points": (ctypes.c_int32, [ctypes.c_double, _c_double_p, _c_double_p, ctypes.c_int32, _VP, _VP,
                                             ctypes.c_double, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),

@@ -11,6 +11,7 @@ error.  Checks:
   - the benchmark's 256 x 256, 2000-step case against central finite
     differences of the GPU forward (h = 1e-6).
 """
+import ctypes
 import dataclasses
 
 import numpy as np
@@ -311,6 +312,59 @@ def test_adjoint_entry_points_validate(gpu):
     np.fill_diagonal(a3, A11)
     three = lattice.Plan(16, 16, 0.45, a3, np.full(3, B1), 0.1 * np.ones((3, 3)))
     assert lib.vdwlb_adjoint_segment(three.handle, F, 4, FB, W, PB, None) == V.E_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert lib.vdwlb_sync_status(h, None) == V.OK
+
+
+def test_adjoint_forward_entry_point(gpu):
+    """vdwlb_adjoint_forward (the last segment's forward, keeping what its
+    reverse sweep needs): its output state equals vdwlb_step's bit for bit,
+    and followed by vdwlb_adjoint_reverse it gives the cotangent and
+    parameter cotangents of vdwlb_adjoint_segment (recompute, then reverse)
+    bit for bit (at the lattice sites; a plane's padding is never written),
+    for an odd and an even step count and with f_out = f_in; it rejects a NULL or misaligned output and a step count below 1 before
+    enqueuing anything."""
+    adjoint, lattice, V = gpu
+    lib = V.lib()
+    P = mixture(2, tau=0.8)
+    nx, ny = 40, 36
+    plan = lattice.Plan(nx, ny, P["kT"], P["a"], P["b"], P["kappa"], P["tau"], P["gamma_mu"], P["lam"], "f64",
+                        P["force"])
+    h, n = plan.handle, plan.state_elems
+    rng = np.random.default_rng(5)
+    rho0 = torch.as_tensor(2.625 * (1 + 0.01 * rng.uniform(-1, 1, (2, ny, nx))), device="cuda")
+    f0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    V.check(lib.vdwlb_init(h, f0.data_ptr(), rho0.data_ptr(), None, None))
+    npar = int(lib.vdwlb_adjoint_param_count(h))
+    fbar0 = torch.as_tensor(rng.standard_normal(n), device="cuda")
+    for nsteps in (7, 12):
+        wsb = int(lib.vdwlb_adjoint_workspace_bytes(h, nsteps)) // 8 + 1
+        # reference: vdwlb_step, and the segment's recompute + reverse
+        a, b = f0.clone(), torch.empty_like(f0)
+        which = ctypes.c_int32()
+        V.check(lib.vdwlb_step(h, a.data_ptr(), b.data_ptr(), nsteps, None, ctypes.byref(which)))
+        f_ref = b if which.value == 1 else a
+        fb_ref, pb_ref = fbar0.clone(), torch.zeros(npar, dtype=torch.float64, device="cuda")
+        ws = torch.empty(wsb, dtype=torch.float64, device="cuda")
+        V.check(lib.vdwlb_adjoint_segment(h, f0.data_ptr(), nsteps, fb_ref.data_ptr(), ws.data_ptr(),
+                                          pb_ref.data_ptr(), None))
+        # forward keeping the moments, then the reverse sweep alone
+        ws2 = torch.empty(wsb, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(f0)
+        V.check(lib.vdwlb_adjoint_forward(h, f0.data_ptr(), nsteps, out.data_ptr(), ws2.data_ptr(), None))
+        fb, pb = fbar0.clone(), torch.zeros(npar, dtype=torch.float64, device="cuda")
+        V.check(lib.vdwlb_adjoint_reverse(h, nsteps, fb.data_ptr(), ws2.data_ptr(), pb.data_ptr(), None))
+        same = f0.clone()
+        V.check(lib.vdwlb_adjoint_forward(h, same.data_ptr(), nsteps, same.data_ptr(), ws2.data_ptr(), None))
+        torch.cuda.synchronize()
+        sites = lambda f: f.view(9, plan.plane, 2)[:, :nx * ny]  # the padding of a plane is never written
+        assert torch.equal(sites(out), sites(f_ref)) and torch.equal(sites(same), sites(f_ref))
+        assert torch.equal(sites(fb), sites(fb_ref)) and torch.equal(pb, pb_ref)
+    ws = torch.empty(int(lib.vdwlb_adjoint_workspace_bytes(h, 4)) // 8 + 1, dtype=torch.float64, device="cuda")
+    out = torch.empty(n + 2, dtype=torch.float64, device="cuda")
+    assert lib.vdwlb_adjoint_forward(h, f0.data_ptr(), 4, None, ws.data_ptr(), None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_forward(h, f0.data_ptr(), 4, out.data_ptr() + 8, ws.data_ptr(), None) == V.E_INVALID_ARG
+    assert lib.vdwlb_adjoint_forward(h, f0.data_ptr(), 0, out.data_ptr(), ws.data_ptr(), None) == V.E_INVALID_ARG
     torch.cuda.synchronize()
     assert lib.vdwlb_sync_status(h, None) == V.OK
 
