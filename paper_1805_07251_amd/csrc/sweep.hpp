@@ -277,6 +277,14 @@ __device__ __forceinline__ double dlog(double x) {
 }
 __device__ __forceinline__ float dlog(float v) { return logf(v); }
 
+// Raises the sticky unphysical-state flag.  The flag only goes from 0 to 1
+// until the host clears it, so a thread that reads it already set skips the
+// atomic: once a state has gone unphysical every later step would otherwise
+// send one atomic per bad site to the same address.
+__device__ __forceinline__ void raise_flag(int* flag) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicOr(flag, 1);
+}
+
 template <typename T>
 __device__ __forceinline__ bool finite_val(T v) {
     return v == v && v - v == T(0);
@@ -568,7 +576,7 @@ k_sweep(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs<C, T
 #pragma unroll
         for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad) raise_flag(flag);
     __syncthreads();
 
     if (x >= g.nx || y >= g.ny) return;
@@ -662,7 +670,7 @@ k_sweep_rows(const T* __restrict__ fin, T* __restrict__ fout, Geometry g, Coeffs
 #pragma unroll
         for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad) raise_flag(flag);
     __syncthreads();
 
     if (x >= g.nx) return;
@@ -772,7 +780,7 @@ __global__ void k_mu_p(const T* __restrict__ rho, T* __restrict__ mu, T* __restr
     kk.force = 0;
     T m[C];
     const bool ok = potential<T, C>(r, l, kk, m);
-    if (!ok) atomicOr(flag, 1);
+    if (!ok) raise_flag(flag);
     if (mu)
 #pragma unroll
         for (int c = 0; c < C; ++c) mu[(int64_t)c * n + s] = m[c];

@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(TX) k_sweep1(const T* __restrict__ fin, T* __r
 #pragma unroll
         for (int c = 0; c < C; ++c) s_phi[c][m] = ph[c];
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad) raise_flag(flag);
     __syncthreads();
 
     if (x >= g.nx) return;
@@ -235,7 +235,7 @@ __global__ void k_mu_p1(const T* __restrict__ rho, T* __restrict__ mu, T* __rest
     kk.gamma = 1.0;
     kk.force = 0;
     T m[C];
-    if (!potential<T, C>(r, l, kk, m)) atomicOr(flag, 1);
+    if (!potential<T, C>(r, l, kk, m)) raise_flag(flag);
     if (mu)
 #pragma unroll
         for (int c = 0; c < C; ++c) mu[(int64_t)c * g.nx + x] = m[c];
