@@ -11,12 +11,17 @@
 // Given the cotangent fb' of the new state, the adjoint runs three gathers:
 //  A (tile, LDS): recompute phi and G at the site from the stored moments;
 //     back-propagate through collision and friction: local density and
-//     momentum cotangents, the force cotangent G0b, the vectors
-//     Av = rho G0b (for the potential gradient) and Bv = G0b (for
-//     theta grad rho), and the Laplacian cotangent of the correction term.
-//  B: phib = div(Av) (transpose of the gradient stencil), mub = gamma phib,
-//     density cotangent through d mu / d rho, total Laplacian cotangent, and
-//     the parameter cotangents (kT, a, b, kappa), reduced per workgroup.
+//     momentum cotangents, the force cotangent G0b and the Laplacian
+//     cotangent of the correction term.
+//  B: phib = div(rho G0b) (transpose of the gradient stencil applied to
+//     Av = rho G0b, formed where it is read), with log forcing also
+//     div(G0b) (for theta grad rho), mub = gamma phib, density cotangent
+//     through d mu / d rho, total Laplacian cotangent, and the parameter
+//     cotangents (kT, a, b, kappa), summed per tile into a running partial.
+//
+// The segment's reverse sweep runs A for its last step and then one fused
+// kernel per earlier step (k_adj_bca: B and C of step t + 1, A of step t);
+// kernels A, B and C separately give the same values bit for bit.
 //  C: rhob = local + B part + Lap(Lb) (the Laplacian is self-adjoint); the
 //     pulled-population cotangent pb_i = (1 - omega) fb'_i + rhob + jb.v_i
 //     is un-streamed: fb_i(x - v_i) = pb_i(x).
