@@ -394,6 +394,26 @@ def adjoint_leg(seed):
         t2 = time.perf_counter()
         fwd.append(t1 - t0)
         bwd.append(t2 - t1)
+    grad = t.grad.cpu().numpy()
+    # the same gradient with every segment's moments kept by the forward
+    # (Spec.keep_moments: no recompute; about 7 GB here)
+    kspec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam,
+                   schedule=sched, keep_moments=True)
+    A.run_and_grad(theta, rho0, kspec, lambda r: ((r[0] - tg) ** 2).sum())
+    kf, kb = [], []
+    for _ in range(3):
+        tk = torch.as_tensor(theta).clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        rho = A.VdwLBFunction.apply(tk, rho0, kspec)
+        kloss = ((rho[0] - tg) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kloss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        kf.append(t1 - t0)
+        kb.append(t2 - t1)
+    kgrad = tk.grad.cpu().numpy()
     # the plain forward for the same 2000 steps (its step graph captured beforehand)
     lat.init(w.rho)
     lat.run(64)
@@ -418,8 +438,14 @@ def adjoint_leg(seed):
         "fwd_plus_bwd_over_plain_forward": (f + b) / pf,
         "adjoint_mlups": sites * 2000 / b / 1e6,
         "loss": float(loss.detach().cpu()),
-        "grad": [float(v) for v in t.grad.cpu().numpy()],
+        "grad": [float(v) for v in grad],
         "theta_names": ["kT", "a11", "a12", "a22", "b1", "b2", "kappa"],
+        "keep_moments": {
+            "forward_ms": min(kf) * 1e3,
+            "backward_ms": min(kb) * 1e3,
+            "fwd_plus_bwd_over_plain_forward": (min(kf) + min(kb)) / pf,
+            "same_gradient_bits": bool(np.array_equal(kgrad, grad)),
+        },
     }
 
 

@@ -4,7 +4,11 @@ checkpointing (the forward keeps the state every `ckpt` steps; the backward
 recomputes each segment from its checkpoint and reverses it).  The last
 segment is never recomputed: the forward runs it with
 vdwlb_adjoint_forward, which keeps its densities and momenta in a
-workspace that the backward reverses first.
+workspace that the backward reverses first.  With Spec.keep_moments the
+forward keeps every segment's that way and the backward recomputes
+nothing: 3 C nx ny doubles per step plus the per-segment fields (about 7 GB
+for 2000 steps of a 256^2 two-component lattice), for callers with the
+memory to spare.
 
 Parameters theta = [kT, a^{cd} (c <= d), b^c, kappa] with the gradient
 matrix kappa^{cd} = kappa * K_hat^{cd} (K_hat fixed), i.e. for two
@@ -65,6 +69,7 @@ class Spec:
     # default) or a schedule index; every schedule gives the same results
     schedule: int | str | None = "auto"
     graphs: bool = False  # replay the backward's recompute / reverse parts from captured hipGraphs
+    keep_moments: bool = False  # keep every segment's moments from the forward: no recompute in the backward
 
 
 class VdwLBFunction(torch.autograd.Function):
@@ -83,27 +88,31 @@ class VdwLBFunction(torch.autograd.Function):
         V.check(V.lib().vdwlb_init(plan.handle, bufs[0].data_ptr(), r0.data_ptr(), None, s), "vdwlb_init")
         _apply_schedule(plan, spec, bufs, s)
         segs = [min(spec.ckpt, spec.nsteps - d) for d in range(0, spec.nsteps, spec.ckpt)]
-        ckpts = []  # the states the recomputed segments (all but the last) start from
+        n_rec = 0 if spec.keep_moments else len(segs) - 1  # segments the backward recomputes (the first n_rec)
+        ckpts = []  # the states they start from
+        kept = []  # workspaces of the other segments, whose moments the forward keeps
         cur = 0
         which = ctypes.c_int32()
-        for m in segs[:-1]:
-            ckpts.append(bufs[cur].clone())
-            V.check(V.lib().vdwlb_step(plan.handle, bufs[cur].data_ptr(), bufs[1 - cur].data_ptr(), m, s,
-                                       ctypes.byref(which)), "vdwlb_step")
-            if which.value == 1:
+        for k, m in enumerate(segs):
+            if k < n_rec:
+                ckpts.append(bufs[cur].clone())
+                V.check(V.lib().vdwlb_step(plan.handle, bufs[cur].data_ptr(), bufs[1 - cur].data_ptr(), m, s,
+                                           ctypes.byref(which)), "vdwlb_step")
+                if which.value == 1:
+                    cur = 1 - cur
+            else:
+                ws = torch.empty(int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, m)) // 8 + 1,
+                                 dtype=torch.float64, device=dev)
+                V.check(V.lib().vdwlb_adjoint_forward(plan.handle, bufs[cur].data_ptr(), m, bufs[1 - cur].data_ptr(),
+                                                      ws.data_ptr(), s), "vdwlb_adjoint_forward")
+                kept.append(ws)
                 cur = 1 - cur
-        # the last segment keeps what its reverse sweep needs
-        ws_last = torch.empty(int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, segs[-1])) // 8 + 1,
-                              dtype=torch.float64, device=dev)
-        V.check(V.lib().vdwlb_adjoint_forward(plan.handle, bufs[cur].data_ptr(), segs[-1], bufs[1 - cur].data_ptr(),
-                                              ws_last.data_ptr(), s), "vdwlb_adjoint_forward")
-        cur = 1 - cur
         C, ny, nx = spec.C, spec.ny, spec.nx
         rho = torch.empty((C, ny, nx), dtype=torch.float64, device=dev)
         mom = torch.empty((C, 2, ny, nx), dtype=torch.float64, device=dev)
         V.check(V.lib().vdwlb_moments(plan.handle, bufs[cur].data_ptr(), rho.data_ptr(), mom.data_ptr(), None, None,
                                       s), "vdwlb_moments")
-        ctx.plan, ctx.spec, ctx.ckpts, ctx.segs, ctx.ws_last = plan, spec, ckpts, segs, ws_last
+        ctx.plan, ctx.spec, ctx.ckpts, ctx.segs, ctx.kept = plan, spec, ckpts, segs, kept
         ctx.forward_done = torch.cuda.Event()
         ctx.forward_done.record(torch.cuda.current_stream(dev))
         ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
@@ -121,22 +130,24 @@ class VdwLBFunction(torch.autograd.Function):
         npar = int(V.lib().vdwlb_adjoint_param_count(plan.handle))
         pbar = torch.zeros(npar, dtype=torch.float64, device=dev)
         segs = ctx.segs
-        torch.cuda.current_stream(dev).wait_event(ctx.forward_done)  # the last segment's workspace
+        n_rec = len(ctx.ckpts)
+        torch.cuda.current_stream(dev).wait_event(ctx.forward_done)  # the kept segments' workspaces
 
-        def reverse_last():  # the last segment first, from the forward's workspace
-            V.check(V.lib().vdwlb_adjoint_reverse(plan.handle, int(segs[-1]), fbar.data_ptr(),
-                                                  ctx.ws_last.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_reverse")
+        def reverse_kept():  # the segments the forward kept, last first
+            for m, ws in zip(reversed(segs[n_rec:]), reversed(ctx.kept)):
+                V.check(V.lib().vdwlb_adjoint_reverse(plan.handle, int(m), fbar.data_ptr(), ws.data_ptr(),
+                                                      pbar.data_ptr(), s), "vdwlb_adjoint_reverse")
 
-        if len(segs) == 1:
-            reverse_last()
+        if n_rec == 0:
+            reverse_kept()
         else:
-            ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(segs[:-1])))
+            ws_bytes = int(V.lib().vdwlb_adjoint_workspace_bytes(plan.handle, max(segs[:n_rec])))
             if os.environ.get("VDWLB_ADJ_SERIAL") != "1":
-                _reverse_overlapped(plan, ctx.ckpts, segs[:-1], fbar, pbar, ws_bytes, dev, first=reverse_last)
+                _reverse_overlapped(plan, ctx.ckpts, segs[:n_rec], fbar, pbar, ws_bytes, dev, first=reverse_kept)
             else:
-                reverse_last()
+                reverse_kept()
                 ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device=dev)
-                for ck, m in zip(reversed(ctx.ckpts), reversed(segs[:-1])):
+                for ck, m in zip(reversed(ctx.ckpts), reversed(segs[:n_rec])):
                     V.check(V.lib().vdwlb_adjoint_segment(plan.handle, ck.data_ptr(), int(m), fbar.data_ptr(),
                                                           ws.data_ptr(), pbar.data_ptr(), s), "vdwlb_adjoint_segment")
         g = pbar.cpu().numpy()

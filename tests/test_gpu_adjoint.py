@@ -374,7 +374,8 @@ def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
     second workspace, while segment k is reversed (vdwlb_adjoint_recompute /
     vdwlb_adjoint_reverse); the gradient equals the one-stream loop of
     vdwlb_adjoint_segment bit for bit, with unequal segments (20 x 4 + 10),
-    with and without graphs, over repeated backward passes."""
+    with and without graphs, over repeated backward passes, and when the
+    forward keeps every segment's moments (Spec.keep_moments: no recompute)."""
     adjoint, _, _ = gpu
     P = mixture(2)
     k_hat = P["kappa"] / 0.1
@@ -392,6 +393,7 @@ def test_overlapped_recompute_equals_one_stream(gpu, monkeypatch):
     monkeypatch.delenv("VDWLB_ADJ_SERIAL")
     runs = [adjoint.run_and_grad(theta, r0, spec, loss_fn) for _ in range(2)]
     runs += [adjoint.run_and_grad(theta, r0, dataclasses.replace(spec, graphs=True), loss_fn) for _ in range(2)]
+    runs.append(adjoint.run_and_grad(theta, r0, dataclasses.replace(spec, keep_moments=True), loss_fn))
     for loss, grad in runs:
         assert loss == serial[0]
         assert np.array_equal(grad, serial[1])
