@@ -337,7 +337,8 @@ vdwlb_status vdwlb_batch_status(vdwlb_batch* batch, int32_t* per_instance, void*
  * Adjoint (reverse-mode derivative) of the sweep, for gradients of a loss on
  * the final densities with respect to the free-energy parameters of Sec. II
  * (kT, a^{cc'}, b^c, kappa^{cc'}) through many steps.  FP64 D2Q9 plans with
- * C = 1 or 2 only (others return VDWLB_E_UNSUPPORTED).
+ * C = 1 to 4 (FP32 and D1Q3 plans return VDWLB_E_UNSUPPORTED); C <= 2 reverses
+ * each step with one fused kernel, C = 3 and 4 with the three separate ones.
  *
  * Parameter cotangent vector (double, device), vdwlb_adjoint_param_count()
  * entries: kT, then a^{cd} for c <= d (row-major upper triangle), then b^c,

@@ -131,6 +131,49 @@ __device__ __forceinline__ double lapg(const double* a, const Geometry& g, int x
     return (4.0 * axis + diag - 20.0 * a[r0 + x]) * (1.0 / 6.0);
 }
 
+// Small dense LU factorisation in place (no pivoting; the friction matrix is
+// symmetric positive definite): the unit lower factor's multipliers below the
+// diagonal, the upper factor on and above it.
+template <int C>
+__device__ __forceinline__ void lu_factor(double (&A)[C][C]) {
+#pragma unroll
+    for (int p = 0; p < C; ++p) {
+        const double ip = 1.0 / A[p][p];
+#pragma unroll
+        for (int q = p + 1; q < C; ++q) {
+            const double f = A[q][p] * ip;
+            A[q][p] = f;
+#pragma unroll
+            for (int m = p + 1; m < C; ++m) A[q][m] -= f * A[p][m];
+        }
+    }
+}
+
+// Solves A x = b in place with the factors of lu_factor.
+template <int C>
+__device__ __forceinline__ void lu_solve(const double (&LU)[C][C], double (&x)[C]) {
+#pragma unroll
+    for (int q = 1; q < C; ++q)
+#pragma unroll
+        for (int p = 0; p < q; ++p) x[q] -= LU[q][p] * x[p];
+#pragma unroll
+    for (int p = C - 1; p >= 0; --p) {
+#pragma unroll
+        for (int m = p + 1; m < C; ++m) x[p] -= LU[p][m] * x[m];
+        x[p] /= LU[p][p];
+    }
+}
+
+// (L u)^c = sum_d W^{cd} (u^c - u^d), the graph Laplacian of the friction weights.
+template <int C>
+__device__ __forceinline__ double graph_laplacian(const double (&W)[C][C], const double (&u)[C], int c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < C; ++d)
+        if (d != c) acc += W[c][d] * (u[c] - u[d]);
+    return acc;
+}
+
 // Local part of the adjoint at one site (collision, friction, force):
 // given the incoming cotangent fin of the site's new populations, its forward
 // moments (rho, j), the potential gradient (dpx, dpy) and the density gradient
@@ -174,6 +217,42 @@ __device__ __forceinline__ void adjoint_local(const double (&fin)[C][Q], const d
         gx[1] -= K * m * d0x;
         gy[0] += K * m * d0y;
         gy[1] -= K * m * d0y;
+    }
+    // C > 2 (Eq. forceFriction): weights W^{cd} = lambda rho^c rho^d / (rho^c + rho^d),
+    // graph Laplacian (L u)^c = sum_d W^{cd} (u^c - u^d), A = diag(rho) + L / 2,
+    // uh = A^-1 (j + G0 / 2) per axis, G = G0 - L uh.  A is factorised once
+    // (LU, no pivoting: it is symmetric positive definite) for both axes and
+    // for the transposed solve of the adjoint below.
+    double Wf[C][C] = {}, LU[C][C] = {}, uhx[C] = {}, uhy[C] = {};
+    if constexpr (C > 2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = c + 1; d < C; ++d) Wf[c][d] = Wf[d][c] = k.lam(c, d) * rho[c] * rho[d] * recip(rho[c] + rho[d]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            double diag = rho[c];
+#pragma unroll
+            for (int d = 0; d < C; ++d)
+                if (d != c) {
+                    diag += 0.5 * Wf[c][d];
+                    LU[c][d] = -0.5 * Wf[c][d];
+                }
+            LU[c][c] = diag;
+        }
+        lu_factor<C>(LU);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            uhx[c] = jx[c] + 0.5 * g0x[c];
+            uhy[c] = jy[c] + 0.5 * g0y[c];
+        }
+        lu_solve<C>(LU, uhx);
+        lu_solve<C>(LU, uhy);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            gx[c] = g0x[c] - graph_laplacian<C>(Wf, uhx, c);
+            gy[c] = g0y[c] - graph_laplacian<C>(Wf, uhy, c);
+        }
     }
 
     // collision adjoint: h = omega [rho M0 + 3 j.M + Q(j)/rho] + 3 G.M
@@ -235,6 +314,44 @@ __device__ __forceinline__ void adjoint_local(const double (&fin)[C][Q], const d
         g0by[0] -= 0.5 * dby * i0;
         rb[1] -= (dbx * (jx[1] + 0.5 * g0x[1]) + dby * (jy[1] + 0.5 * g0y[1])) * i1 * i1;
         rb[0] += (dbx * (jx[0] + 0.5 * g0x[0]) + dby * (jy[0] + 0.5 * g0y[0])) * i0 * i0;
+    }
+    if constexpr (C > 2) {
+        // G = G0 - L uh, uh = A^-1 r, r = j + G0/2, per axis with the cotangent
+        // Gb of G: ub = -L Gb, rb = A^-1 ub (A symmetric), jb += rb,
+        // G0b = Gb + rb/2; matrix cotangents Ab = -rb uh^T, Lb = -Gb uh^T
+        // (both axes), then A = diag(rho) + L/2 and L(W), W(rho).
+        double rbx[C], rby[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            rbx[c] = -graph_laplacian<C>(Wf, gbx, c);
+            rby[c] = -graph_laplacian<C>(Wf, gby, c);
+        }
+        lu_solve<C>(LU, rbx);
+        lu_solve<C>(LU, rby);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            jbx[c] += rbx[c];
+            jby[c] += rby[c];
+            g0bx[c] += 0.5 * rbx[c];
+            g0by[c] += 0.5 * rby[c];
+            // Ab_cc = -(rb_c uh_c) over both axes, into rho^c through diag(rho)
+            rb[c] -= rbx[c] * uhx[c] + rby[c] * uhy[c];
+        }
+        // Lb_ab = -Gb_a uh_b - (rb_a uh_b) / 2; W^{cd} enters L_cc, L_dd with +1
+        // and L_cd, L_dc with -1
+        auto Lb = [&](int a, int b) {
+            return -(gbx[a] * uhx[b] + gby[a] * uhy[b]) - 0.5 * (rbx[a] * uhx[b] + rby[a] * uhy[b]);
+        };
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = c + 1; d < C; ++d) {
+                const double wb = (Lb(c, c) + Lb(d, d)) - (Lb(c, d) + Lb(d, c));
+                const double s2 = recip(rho[c] + rho[d]);
+                const double lw = k.lam(c, d) * wb * s2 * s2;
+                rb[c] += lw * rho[d] * rho[d];
+                rb[d] += lw * rho[c] * rho[c];
+            }
     }
     // force adjoint, local part: G0 = -rho grad phi (+ theta grad rho)
 #pragma unroll
@@ -964,7 +1081,7 @@ template <int C>
 hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* const (&bufs)[2],
                          hipStream_t s, bool fused) {
     StepKernels<C> K(p, L, ws, s);
-    if (!fused) {
+    if (C > 2 || !fused) {  // the fused kernel's LDS holds C <= 2
         for (int t = nsteps - 1, k = 0; t >= 0; --t, ++k) {
             K.a(t, bufs[k & 1]);
             K.b(t, t < nsteps - 1);
@@ -972,10 +1089,12 @@ hipError_t reverse_steps(const vdwlb_plan& p, const Layout& L, double* ws, int n
         }
         return hipGetLastError();
     }
-    K.a(nsteps - 1, bufs[0]);
-    // the running partials start with the last step's (each kernel adds step t + 1's)
-    for (int t = nsteps - 2, k = 1; t >= 0; --t, ++k) K.bca(t, bufs[(k - 1) & 1], bufs[k & 1], t < nsteps - 2);
-    K.bc(bufs[(nsteps - 1) & 1], bufs[nsteps & 1], nsteps > 1);
+    if constexpr (C <= 2) {
+        K.a(nsteps - 1, bufs[0]);
+        // the running partials start with the last step's (each kernel adds step t + 1's)
+        for (int t = nsteps - 2, k = 1; t >= 0; --t, ++k) K.bca(t, bufs[(k - 1) & 1], bufs[k & 1], t < nsteps - 2);
+        K.bc(bufs[(nsteps - 1) & 1], bufs[nsteps & 1], nsteps > 1);
+    }
     return hipGetLastError();
 }
 
@@ -997,8 +1116,10 @@ hipError_t enqueue_recompute(const vdwlb_plan& p, const Layout& L, double* ws, i
 hipError_t enqueue_reverse(const vdwlb_plan& p, const Layout& L, double* ws, int nsteps, double* fbar_io,
                            double* pbar, hipStream_t s, bool fused) {
     double* const bufs[2] = {fbar_io, ws + L.fb};
-    hipError_t e = p.C == 1 ? reverse_steps<1>(p, L, ws, nsteps, bufs, s, fused)
-                            : reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused);
+    hipError_t e = p.C == 1   ? reverse_steps<1>(p, L, ws, nsteps, bufs, s, fused)
+                   : p.C == 2 ? reverse_steps<2>(p, L, ws, nsteps, bufs, s, fused)
+                   : p.C == 3 ? reverse_steps<3>(p, L, ws, nsteps, bufs, s, fused)
+                              : reverse_steps<4>(p, L, ws, nsteps, bufs, s, fused);
     if (e == hipSuccess) {  // the parameter cotangents of the whole segment, in a fixed order
         hipLaunchKernelGGL(adj::k_adj_reduce, dim3(L.np), dim3(adj::BLK), 0, s, (const double*)(ws + L.partial),
                            L.tiles, L.np, pbar);
@@ -1088,7 +1209,7 @@ hipError_t scratch_address(int device, void** out) {
 vdwlb_status check_adjoint(const vdwlb_plan* p, int32_t nsteps, const void* workspace) {
     if (!p || !workspace || nsteps < 1) return VDWLB_E_INVALID_ARG;
     if (!state_aligned(*p, workspace)) return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+    if (p->dtype != VDWLB_F64 || p->C > 4 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     const Layout L = layout(*p, nsteps);
     if ((int64_t)nsteps * L.tiles > 0x7fffffff) return VDWLB_E_INVALID_ARG;  // partial-sum count of the segment
     return VDWLB_OK;
@@ -1108,17 +1229,22 @@ size_t vdwlb_adjoint_workspace_bytes(const vdwlb_plan* p, int32_t nsteps) {
 vdwlb_status vdwlb_moments_adjoint(vdwlb_plan* p, const void* rho_bar, const void* mom_bar, void* fbar,
                                    void* stream) {
     if (!p || !fbar || (!rho_bar && !mom_bar) || !state_aligned(*p, fbar)) return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+    if (p->dtype != VDWLB_F64 || p->C > 4 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     const Geometry g = adjoint_geometry(*p);
     const int nb = (int)(((int64_t)p->nx * p->ny + adj::BLK - 1) / adj::BLK);
     hipError_t e = hipMemsetAsync(fbar, 0, vdwlb_state_bytes(p), (hipStream_t)stream);
     if (e != hipSuccess) return set_device_error(e, "moments adjoint");
+    const double* rb = (const double*)rho_bar;
+    const double* mb = (const double*)mom_bar;
+    hipStream_t s = (hipStream_t)stream;
     if (p->C == 1)
-        hipLaunchKernelGGL((adj::k_moments_adj<1>), dim3(nb), dim3(adj::BLK), 0, (hipStream_t)stream,
-                           (const double*)rho_bar, (const double*)mom_bar, (double*)fbar, g);
+        hipLaunchKernelGGL((adj::k_moments_adj<1>), dim3(nb), dim3(adj::BLK), 0, s, rb, mb, (double*)fbar, g);
+    else if (p->C == 2)
+        hipLaunchKernelGGL((adj::k_moments_adj<2>), dim3(nb), dim3(adj::BLK), 0, s, rb, mb, (double*)fbar, g);
+    else if (p->C == 3)
+        hipLaunchKernelGGL((adj::k_moments_adj<3>), dim3(nb), dim3(adj::BLK), 0, s, rb, mb, (double*)fbar, g);
     else
-        hipLaunchKernelGGL((adj::k_moments_adj<2>), dim3(nb), dim3(adj::BLK), 0, (hipStream_t)stream,
-                           (const double*)rho_bar, (const double*)mom_bar, (double*)fbar, g);
+        hipLaunchKernelGGL((adj::k_moments_adj<4>), dim3(nb), dim3(adj::BLK), 0, s, rb, mb, (double*)fbar, g);
     e = hipGetLastError();
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, "moments adjoint");
 }
@@ -1204,7 +1330,7 @@ vdwlb_status vdwlb_adjoint_segment(vdwlb_plan* p, const void* f_ckpt, int32_t ns
 vdwlb_status vdwlb_adjoint_segment_noalloc(vdwlb_plan* p, const void* f_ckpt, int32_t nsteps, void* fbar_io,
                                            double* pbar_accum, void* stream) {
     if (!p || nsteps < 1) return VDWLB_E_INVALID_ARG;
-    if (p->dtype != VDWLB_F64 || p->C > 2 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
+    if (p->dtype != VDWLB_F64 || p->C > 4 || p->dim != 2) return VDWLB_E_UNSUPPORTED;
     if (!f_ckpt || !fbar_io || !pbar_accum || !state_aligned(*p, f_ckpt) || !state_aligned(*p, fbar_io))
         return VDWLB_E_INVALID_ARG;
     if (vdwlb_adjoint_workspace_bytes(p, nsteps) > VDWLB_ADJOINT_SCRATCH_BYTES) return VDWLB_E_CAPACITY;

@@ -64,7 +64,7 @@ hipError_t run_sweep(const vdwlb_plan& p, const void* fin, void* fout, hipStream
     const Geometry g = make_geometry(p, TX, TY);
     const Coeffs<C, T> k = make_coeffs<C, T>(p);
     const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
-    if (mom) {  // the adjoint's recompute: FP64, C <= 2 only
+    if (mom) {  // the adjoint's recompute: FP64; C > 2 goes through run_sweep_mom_fixed
         if constexpr (std::is_same<T, double>::value && C <= 2) {
             if (p.tau == 1.0)
                 launch_tile<T, C, TX, TY, NTS, OCC, true, true, RY>(p, fin, fout, s, mom, g, k, tiles);
@@ -114,6 +114,25 @@ hipError_t run_sweep1(const vdwlb_plan& p, const void* fin, void* fout, hipStrea
     return hipGetLastError();
 }
 
+// The sweep that also writes the moments, for C > 2: one tile shape (every
+// schedule gives the same states bit for bit, so the adjoint's recompute
+// need not follow the plan's).
+template <typename T, int C>
+hipError_t run_sweep_mom_fixed(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
+    if constexpr (std::is_same<T, double>::value) {
+        constexpr int TX = 32, TY = 8;
+        const Geometry g = make_geometry(p, TX, TY);
+        const Coeffs<C, T> k = make_coeffs<C, T>(p);
+        const int tiles = g.tiles_x * ((p.ny + TY - 1) / TY);
+        if (p.tau == 1.0)
+            launch_tile<T, C, TX, TY, true, 0, true, true, 1>(p, fin, fout, s, mom, g, k, tiles);
+        else
+            launch_tile<T, C, TX, TY, true, 0, false, true, 1>(p, fin, fout, s, mom, g, k, tiles);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int C>
 hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t s, void* mom) {
     if (p.dim == 1) {
@@ -126,6 +145,7 @@ hipError_t run_any(const vdwlb_plan& p, const void* fin, void* fout, hipStream_t
             default: return hipErrorInvalidValue;
         }
     }
+    if (mom && C > 2) return run_sweep_mom_fixed<T, C>(p, fin, fout, s, mom);
     return run_sweep_sched<T, C>(p, fin, fout, s, mom);
 }
 
