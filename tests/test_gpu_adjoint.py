@@ -283,8 +283,9 @@ def test_graph_replayed_segments_equal_eager(gpu, monkeypatch):
 
 def test_adjoint_entry_points_validate(gpu):
     """The segment, recompute and reverse entry points reject a step count
-    below 1 and misaligned buffers, and report FP32 and D1Q3 plans
-    as unsupported, all before any launch."""
+    below 1 and misaligned buffers, and report FP32 and D1Q3 plans as
+    unsupported, all before any launch; the graph-replay switch takes 0 or 1
+    only."""
     adjoint, lattice, V = gpu
     lib = V.lib()
     a = np.array([[A11, 0.9 * A11], [0.9 * A11, A11]])
@@ -304,6 +305,9 @@ def test_adjoint_entry_points_validate(gpu):
     assert lib.vdwlb_adjoint_recompute(h, F, 4, W + 8, None) == V.E_INVALID_ARG
     assert lib.vdwlb_adjoint_reverse(h, 4, FB + 8, W, PB, None) == V.E_INVALID_ARG
     assert lib.vdwlb_adjoint_reverse(h, 4, FB, W, None, None) == V.E_INVALID_ARG
+    assert lib.vdwlb_set_adjoint_graphs(h, 2) == V.E_INVALID_ARG
+    assert lib.vdwlb_set_adjoint_graphs(None, 1) == V.E_INVALID_ARG
+    assert lib.vdwlb_set_adjoint_graphs(h, 1) == V.OK and lib.vdwlb_set_adjoint_graphs(h, 0) == V.OK
     for kw in (dict(dtype="f32"), dict(dim=1)):
         other = lattice.Plan(16, 16 if kw.get("dim", 2) == 2 else 1, 0.45, a, np.array([B1, B1]),
                              0.1 * np.ones((2, 2)), **kw)
