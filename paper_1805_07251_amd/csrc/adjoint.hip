@@ -671,9 +671,9 @@ __global__ void __launch_bounds__(NTF) k_adj_bca(const double* __restrict__ fbn,
     constexpr int RING2 = X2 * Y2 - TX * TY;
     static_assert(RING2 <= NTF - NT, "one radius-2 ring site per thread of the upper half");
     static_assert(X1 * Y1 <= NTF, "one potential site per thread");
-    __shared__ double s_av[2 * C][X3 * Y3];
-    __shared__ double s_bv[2 * C][X3 * Y3];
-    __shared__ double s_rn[C][X3 * Y3];  // densities of step t + 1
+    __shared__ double s_av[2 * C][X3 * Y3];  // rho G0b of step t + 1, formed when staged
+    __shared__ double s_bv[2 * C][X3 * Y3];  // G0b of step t + 1 (log forcing; 0 for nid)
+    __shared__ double s_rn[C][X3 * Y3];      // densities of step t + 1
     __shared__ double s_rbb[C][X2 * Y2];
     __shared__ double s_lbt[C][X2 * Y2];
     __shared__ double s_rb[C][X1 * Y1];
