@@ -497,11 +497,17 @@ __device__ __forceinline__ void reduce_partial_wave(const double (&s_red)[NP][NT
         for (int q = 0; q < NP; ++q) out[q] = accumulate ? prev[q] + v[q] : v[q];
 }
 
-// Tile origin of workgroup b (row-major tiles).
+// Tile origin of workgroup b.  Workgroup b runs on XCD b mod 8; when the tile
+// count divides by 8 each XCD gets a contiguous range of row-major tiles, so
+// the rings a tile reads were written by the same XCD (its L2) except at the
+// range's first and last tile rows.  Every launch maps b to the same tile, so a
+// tile's running parameter partial stays with its workgroup index.
 __device__ __forceinline__ void tile_origin(const Geometry& g, int& x0, int& y0) {
     const int tiles_x = (g.nx + TX - 1) / TX;
-    x0 = (blockIdx.x % tiles_x) * TX;
-    y0 = (blockIdx.x / tiles_x) * TY;
+    const int n = gridDim.x, b = blockIdx.x;
+    const int t = (n % 8 == 0) ? (b & 7) * (n >> 3) + (b >> 3) : b;
+    x0 = (t % tiles_x) * TX;
+    y0 = (t / tiles_x) * TY;
 }
 
 // Writes the local adjoint of one site into the step's fields.
