@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: the headline sweep for --steps steps and the 1 GiB copy kernel only")
     ap.add_argument("--schedule", type=int, default=-1,
-                    help="with --profile: use this sweep schedule instead of autotuning")
+                    help="with --profile or --legs adjoint: use this sweep schedule instead of autotuning")
     ap.add_argument("--phase", action="store_true",
                     help="profiling run: the 256 x 256 Appendix A phase-diagram leg only")
     ap.add_argument("--legs", default="",
@@ -362,7 +362,7 @@ def batch_d1q3_leg(seed, steps):
     }
 
 
-def adjoint_leg(seed):
+def adjoint_leg(seed, schedule=-1):
     """Gradient of a density-profile loss after 2000 steps of the 256 x 256
     lattice w.r.t. (kT, a11, a12, a22, b1, b2, kappa), checkpoints every 100."""
     import numpy as np
@@ -373,11 +373,15 @@ def adjoint_leg(seed):
     from paper_1805_07251_amd.lattice import Lattice
 
     w, tgt = I.adjoint_case(seed)
-    # the plain forward on the autotuner's schedule; the adjoint's forward and
-    # recompute run the same schedule
+    # the plain forward on the autotuner's schedule (or the one asked for); the
+    # adjoint's forward and recompute run the same schedule
     lat = Lattice.from_workload(w)
     lat.init(w.rho)
-    sched = lat.autotune()
+    if schedule >= 0:
+        lat.set_schedule(schedule)
+        sched = schedule
+    else:
+        sched = lat.autotune()
     theta = A.theta_from_params(w.kT, w.a, w.b, I.KAPPA)
     spec = A.Spec(w.nx, w.ny, 2, w.kappa / I.KAPPA, 2000, ckpt=100, tau=w.tau, gamma_mu=w.gamma_mu, lam=w.lam,
                   schedule=sched)
@@ -674,7 +678,7 @@ LEGS = {
     "batched": lambda a: batch_leg(a.seed, 20000, 10),
     "d1q3_line_16M_f64": lambda a: sweep_line(_inputs().line_spinodal(a.seed, L=1 << 24), "f64", 2000, a.warmup),
     "batched_d1q3": lambda a: batch_d1q3_leg(a.seed, 50000),
-    "adjoint": lambda a: adjoint_leg(a.seed),
+    "adjoint": lambda a: adjoint_leg(a.seed, a.schedule if a.legs else -1),
     "copy": lambda a: {"gbs": copy_gbs(reps=5), "bytes": 1 << 30},
 }
 
