@@ -243,9 +243,16 @@ vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, doubl
  *   info    device int32 [n][4]: status, iterations (all searches), the number of distinct
  *           phases whose Hessian is not positive definite (before the polish),
  *           polish (0 none, 1 accepted, 2 rejected: search values kept), written.
+ * The searches run in passes with growing iteration budgets; the points still
+ * searching after a pass go on in the next one, packed densely (the results
+ * are those of uninterrupted searches, bit for bit).  Until the classification
+ * writes it, phases holds the state of the searches in progress.  The call
+ * takes a stream-ordered workspace of 4 (64 + 2 n) bytes (hipMallocAsync on
+ * stream, freed on stream after the last kernel).
  * VDWLB_E_INVALID_ARG for kT or threshold not positive and finite, a not finite
  * or not symmetric, b not positive, n < 0, max_iter < 1, or a NULL pointer when
- * n > 0.  Asynchronous on stream. */
+ * n > 0; a device error if the workspace cannot be allocated.  Asynchronous on
+ * stream. */
 vdwlb_status vdwlb_phase_points(double kT, const double* a, const double* b, int32_t n, const double* NA,
                                 const double* NB, double threshold, int32_t max_iter, double* phases, double* raw,
                                 double* F, int32_t* info, void* stream);

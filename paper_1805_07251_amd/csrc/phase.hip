@@ -21,6 +21,7 @@
 //      the other two.
 // Bulk free-energy density f = sum_c rho^c kT ln(rho^c / (1 - eta))
 // - sum_cc' a^{cc'} rho^c rho^c' (Eq. continuousFreeEnergy without gradients).
+#include <climits>
 #include <cmath>
 #include <cstdint>
 
@@ -32,9 +33,18 @@ namespace {
 
 constexpr int PH_BLOCK = 64;             // one wave per workgroup: waves finish independently
 constexpr int PH_GROUP = 16;             // lanes per point in the search (12 trial moves)
-constexpr int PH_POINTS = PH_BLOCK / PH_GROUP;  // points per search workgroup
 constexpr int PH_RESTARTS = 2;           // restarts of step 6(b) per point
+// Iteration budgets of the search passes before the last (which has none): a
+// pass ends when its slowest point has spent its budget, and the points still
+// searching go on in the next pass, packed into fewer waves.
+constexpr int PH_PASS_ITERS[] = {20000, 40000, 80000, 160000};
+constexpr int PH_PASSES = sizeof(PH_PASS_ITERS) / sizeof(PH_PASS_ITERS[0]);
+// Passes from this one on run workgroups of four waves, which the hardware
+// spreads over the four SIMDs of one CU: with the few waves of the later
+// passes, each long search then has a SIMD to itself.
+constexpr int PH_WIDE = 256, PH_WIDE_FROM = 1;
 constexpr int PH_MAX_ITER = 700000000;   // iterations of one search; (1 + PH_RESTARTS) of them fit an int32
+static_assert((1 + PH_RESTARTS) * (long long)PH_MAX_ITER < INT_MAX, "the last pass's budget never runs out");
 constexpr double MERGE_TOL = 1e-3;       // phases closer than this (max norm, relative to max(1, |rho|)) are one
 constexpr double VOLUME_MIN = 1e-6;      // merged phases with less volume are dropped
 constexpr double F_SLACK = 1e-12;        // a polish may not raise the free energy by more (relative to max(1, |F|))
@@ -389,18 +399,26 @@ constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_STABLE_PENDING
 // lexicographic minimum of (free energy, lane) -- the first strict minimum,
 // as the serial scan finds it -- and every lane applies the winning move
 // with the winner's phase energies, so z, F and the step stay identical in
-// all lanes of the group.  Returns the final total free energy and adds the
-// iterations to iters.
-__device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double threshold, int max_iter, int& iters,
-                                int lane) {
+// all lanes of the group.
+//
+// The search is resumable: (z, step, it) is its whole state, since the
+// phase energies are a function of z (recomputing them gives the values the
+// accepted moves produced, bit for bit).  Runs from that state until the
+// step falls below threshold or it reaches max_iter (returns true: the search
+// has ended), or until budget more iterations have run (returns false; the
+// state then continues the search exactly).  F receives the total free
+// energy of z; iterations are added to iters.
+__device__ bool search_run(const Mix& m, Rho N, double (&z)[6], double& step, int& it, double threshold,
+                           int max_iter, int& budget, int& iters, int lane, double& F) {
     double e1 = phase_energy(m, z[0], z[1], z[2]);
     double e2 = phase_energy(m, z[3], z[4], z[5]);
     double e3 = phase_energy(m, N.a - z[0] - z[3], N.b - z[1] - z[4], 1.0 - z[2] - z[5]);
-    double F = (e1 + e2) + e3;
-    double step = 0.01;
+    F = (e1 + e2) + e3;
     const int k = lane >> 1;
     const bool trial = lane < 12, minus = (lane & 1) != 0;
-    for (int it = 0; it < max_iter; ++it) {
+    for (; it < max_iter; ++it) {
+        if (budget == 0) return false;
+        --budget;
         ++iters;
         double Ft = INFINITY, t1 = e1, t2 = e2, t3 = e3;
         if (trial) {
@@ -441,10 +459,10 @@ __device__ double direct_search(const Mix& m, Rho N, double (&z)[6], double thre
             e3 = w3;
         } else {
             step *= 0.5;
-            if (step < threshold) break;
+            if (step < threshold) return true;
         }
     }
-    return F;
+    return true;
 }
 
 // Step 6(b): if the distinct phases of the search's end state z include an
@@ -482,23 +500,52 @@ __device__ __noinline__ bool restart_start(const Mix& m, Rho N, double (&z)[6]) 
 // search, and, while the search ends with an unstable distinct phase (at most
 // PH_RESTARTS times), a new search with the largest unstable phase split
 // along its unstable direction into phases 1 and 2 and phase 3 holding the
-// other phases packed together.  PH_GROUP lanes per point (PH_POINTS points
-// per workgroup; every lane of a group takes the same decisions, lane 0
-// writes).  Writes the last search's three phases (rho_A, rho_B, V) to raw,
-// its free energy to F and (status, iterations of all searches) to info[0..1].
-__global__ void __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
-k_phase_search(Mix m, int n, const double* __restrict__ NA,
-                                                          const double* __restrict__ NB, double threshold,
-                                                          int max_iter, double* __restrict__ raw,
-                                                          double* __restrict__ Fout, int* __restrict__ info) {
+// other phases packed together.  PH_GROUP lanes per point (every lane of a
+// group takes the same decisions, lane 0 writes); a workgroup of one or four
+// waves.
+//
+// One launch is one pass over a work list.  The first pass (list_in null)
+// takes every point, tests its stability and starts its search; a later
+// pass takes the points of list_in[0 .. *count_in) and resumes their
+// searches from state.  A point runs until its searches end or budget
+// iterations of this pass are spent; in the latter case lane 0 stores
+// (z, step, it, restart) in state[i][0..8], the iterations so far in info[i][1],
+// and appends i to list_out.  A point whose searches have ended writes the
+// last search's three phases (rho_A, rho_B, V) to raw, its free energy to F
+// and (status, iterations of all searches) to info[0..1].  Splitting the
+// searches into passes keeps the results of one uninterrupted search bit for
+// bit; it lets each pass start the remaining long searches in waves of their
+// own, instead of leaving them to share SIMDs with waves of points that
+// happened to sit next to them in the grid.
+__global__ void __launch_bounds__(PH_WIDE) __attribute__((amdgpu_waves_per_eu(4)))
+k_phase_search(Mix m, int n, const double* __restrict__ NA, const double* __restrict__ NB, double threshold,
+               int max_iter, int budget, const int* __restrict__ list_in, const int* __restrict__ count_in,
+               int* __restrict__ list_out, int* __restrict__ count_out, double* __restrict__ state,
+               double* __restrict__ raw, double* __restrict__ Fout, int* __restrict__ info) {
     const int lane = threadIdx.x & (PH_GROUP - 1);
-    const int i = blockIdx.x * PH_POINTS + (int)(threadIdx.x / PH_GROUP);
-    if (i >= n) return;  // whole groups leave together
+    const int slot = (int)((blockIdx.x * blockDim.x + threadIdx.x) / PH_GROUP);
+    int i = slot;
+    if (list_in) {
+        if (slot >= *count_in) return;  // whole groups leave together
+        i = list_in[slot];
+    } else if (slot >= n) {
+        return;
+    }
     const Rho N{NA[i], NB[i]};
-    double F = NAN;
-    int status = ST_INVALID, iters = 0;
+    double F = NAN, step = 0.01;
+    int status = ST_INVALID, iters = 0, it = 0, restart = 0;
     double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (admissible(m, N)) {
+    bool searching = false;
+    if (list_in) {
+        const double* q = state + (int64_t)i * 9;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) z[j] = q[j];
+        step = q[6];
+        it = (int)q[7];
+        restart = (int)q[8];
+        iters = info[(int64_t)i * 4 + 1];
+        searching = true;
+    } else if (admissible(m, N)) {
         F = free_density(m, N);
         const Sym2 h = hessian(m, N);
         if (h.xx > 0.0 && h.xx * h.yy - h.xy * h.xy > 0.0) {
@@ -518,12 +565,30 @@ k_phase_search(Mix m, int n, const double* __restrict__ NA,
             z[3] = N.a - z[0];
             z[4] = N.b - z[1];
             z[5] = V12;
-            for (int restart = 0;; ++restart) {
-                F = direct_search(m, N, z, threshold, max_iter, iters, lane);
-                if (!isfinite(F) || restart == PH_RESTARTS || !restart_start(m, N, z)) break;
-            }
-            status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
+            searching = true;
         }
+    }
+    if (searching) {
+        for (;;) {
+            if (!search_run(m, N, z, step, it, threshold, max_iter, budget, iters, lane, F)) {
+                if (lane == 0) {
+                    double* q = state + (int64_t)i * 9;
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) q[j] = z[j];
+                    q[6] = step;
+                    q[7] = (double)it;
+                    q[8] = (double)restart;
+                    info[(int64_t)i * 4 + 1] = iters;
+                    list_out[atomicAdd(count_out, 1)] = i;
+                }
+                return;
+            }
+            if (!isfinite(F) || restart == PH_RESTARTS || !restart_start(m, N, z)) break;
+            ++restart;
+            step = 0.01;
+            it = 0;
+        }
+        status = isfinite(F) ? ST_SEARCHED : ST_FAILED;
     }
     if (lane != 0) return;
     double* w = raw + (int64_t)i * 9;
@@ -543,6 +608,11 @@ k_phase_search(Mix m, int n, const double* __restrict__ NA,
     Fout[i] = F;
     info[(int64_t)i * 4 + 0] = status;
     info[(int64_t)i * 4 + 1] = iters;
+}
+
+__global__ void k_phase_zero(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Steps 3 and 4: classification and polish of the searched points, one
@@ -653,14 +723,34 @@ extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const dou
     const Mix m{kT, a[0], a[1], a[3], b[0], b[1]};
     const unsigned nb = (unsigned)((n + PH_BLOCK - 1) / PH_BLOCK);
     const hipStream_t s = (hipStream_t)stream;
-    const unsigned nbs = (unsigned)((n + PH_POINTS - 1) / PH_POINTS);
-    hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, threshold, (int)max_iter,
-                       raw, F, (int*)info);
-    hipError_t e = hipGetLastError();
+    // stream-ordered workspace: one counter per pass, then two work lists of n
+    // points (ping-pong between passes); the search state of a point that
+    // goes on to the next pass is kept in its row of phases, which only the
+    // classification writes afterwards
+    int* ws = nullptr;
+    hipError_t e = hipMallocAsync((void**)&ws, sizeof(int) * (64 + 2 * (size_t)n), s);
+    if (e != hipSuccess) return set_device_error(e, "phase-point workspace");
+    int* const count = ws;
+    int* const list[2] = {ws + 64, ws + 64 + n};
+    hipLaunchKernelGGL(k_phase_zero, dim3(1), dim3(64), 0, s, count, PH_PASSES + 1);
+    e = hipGetLastError();
+    for (int p = 0; p <= PH_PASSES && e == hipSuccess; ++p) {
+        const bool last = p == PH_PASSES;
+        const int block = p < PH_WIDE_FROM ? PH_BLOCK : PH_WIDE, points = block / PH_GROUP;
+        const unsigned nbs = (unsigned)((n + points - 1) / points);
+        hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(block), 0, s, m, (int)n, NA, NB, threshold,
+                           (int)max_iter, last ? INT_MAX : PH_PASS_ITERS[p],
+                           p == 0 ? (const int*)nullptr : (const int*)list[(p - 1) & 1],
+                           p == 0 ? (const int*)nullptr : (const int*)(count + p), last ? nullptr : list[p & 1],
+                           last ? nullptr : count + p + 1, phases, raw, F, (int*)info);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_phase_classify, dim3(nb), dim3(PH_BLOCK), 0, s, m, (int)n, NA, NB, (const double*)raw,
                            (const double*)F, phases, (int*)info);
         e = hipGetLastError();
     }
+    const hipError_t ef = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = ef;
     return e == hipSuccess ? VDWLB_OK : set_device_error(e, "phase-point kernels");
 }

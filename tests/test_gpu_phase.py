@@ -34,10 +34,13 @@ def baseline():
 
 @pytest.fixture(scope="module")
 def oracle_points():
-    """The oracle pipeline at a three-phase, two two-phase, two stable and one
-    invalid point of the baseline mixture (about 20 s of CPU)."""
+    """The oracle pipeline at two three-phase, two two-phase, two stable and
+    one invalid point of the baseline mixture (about 40 s of CPU).  The
+    searches of (0.8, 0.8) and (0.673828125, 0.861328125) run about 28,000
+    and 68,000 iterations, so on the GPU they resume across one and two of
+    the search's passes (budgets of 20,000 then 40,000 iterations)."""
     a, b = baseline()
-    pts = [(0.8, 0.8), (2.0, 0.5), (0.5, 2.0), (0.3, 0.3), (0.05, 0.05), (2.0, 1.5)]
+    pts = [(0.8, 0.8), (2.0, 0.5), (0.5, 2.0), (0.3, 0.3), (0.05, 0.05), (2.0, 1.5), (0.673828125, 0.861328125)]
     return pts, [T.phase_point(NA, NB, KT, a, b) for NA, NB in pts]
 
 
@@ -135,6 +138,23 @@ def test_baseline_grid_properties(phase, oracle_points):
             assert np.all(np.linalg.eigvalsh(T.hessian(r, KT, a, b)) > 0), (N, r)
         if st[k] == 3:
             np.testing.assert_allclose(ph[:, :2], three, rtol=0, atol=1e-10)
+
+
+def test_points_independent_of_batch(phase):
+    """A point's outputs do not depend on the other points of the call: the
+    searches run in passes that pack the unfinished points into work lists
+    in whatever order their groups finish, so the 28 x 28 grid, the same grid
+    reversed and every third point alone must agree bit for bit."""
+    a, b = baseline()
+    NA, NB = phase.composition_grid(b, 28)
+    NA, NB = np.asarray(NA), np.asarray(NB)
+    full = host(phase.phase_points(KT, a, b, NA, NB))
+    rev = host(phase.phase_points(KT, a, b, NA[::-1].copy(), NB[::-1].copy()))
+    sub = host(phase.phase_points(KT, a, b, NA[::3].copy(), NB[::3].copy()))
+    assert np.count_nonzero(full["iterations"] > 20000) >= 5  # searches that resume in a later pass
+    for k in ("phases", "raw", "F", "status", "iterations", "n_unstable", "polished"):
+        assert full[k][::-1].tobytes() == rev[k].tobytes(), k
+        assert full[k][::3].tobytes() == sub[k].tobytes(), k
 
 
 def test_iteration_cap_and_invalid_points(phase):
