@@ -391,6 +391,22 @@ __device__ __forceinline__ int count_unstable(const Mix& m, const Phase (&P)[3],
 // 1..3 phases) are final; the others mark work still to do.
 constexpr int ST_INVALID = -1, ST_FAILED = 0, ST_SEARCHED = 4, ST_STABLE_PENDING = 6;
 
+// One step of a lexicographic (value, lane) minimum across lanes: each lane
+// takes the pair of the lane that the DPP control CTRL names (all lanes read
+// a lane of their own row of 16) if that pair is smaller.
+template <int CTRL>
+__device__ __forceinline__ void row_min_step(double& best, int& bl) {
+    const long long b = __double_as_longlong(best);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const double ob = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    const int ol = __builtin_amdgcn_update_dpp(0, bl, CTRL, 0xF, 0xF, false);
+    if (ob < best || (ob == best && ol < bl)) {
+        best = ob;
+        bl = ol;
+    }
+}
+
 // The direct search from the amounts z = (A1, B1, V1, A2, B2, V2), phase 3
 // holding the rest of N, run by a group of PH_GROUP lanes: lane l < 12 owns
 // the trial move of variable l / 2 by +step (l even) or -step (l odd), the
@@ -420,7 +436,7 @@ __device__ bool search_run(const Mix& m, Rho N, double (&z)[6], double& step, in
         if (budget == 0) return false;
         --budget;
         ++iters;
-        double Ft = INFINITY, t1 = e1, t2 = e2, t3 = e3;
+        double Ft = INFINITY, em = INFINITY, t3 = e3;
         if (trial) {
             const double mv = minus ? -step : step;
             double t[6];
@@ -429,33 +445,33 @@ __device__ bool search_run(const Mix& m, Rho N, double (&z)[6], double& step, in
             // the moved phase (1 or 2) selected first, so that all trial lanes
             // run one phase-energy evaluation instead of both branches
             const bool first = k < 3;
-            const double em = phase_energy(m, first ? t[0] : t[3], first ? t[1] : t[4], first ? t[2] : t[5]);
-            t1 = first ? em : e1;
-            t2 = first ? e2 : em;
+            em = phase_energy(m, first ? t[0] : t[3], first ? t[1] : t[4], first ? t[2] : t[5]);
             t3 = phase_energy(m, N.a - t[0] - t[3], N.b - t[1] - t[4], 1.0 - t[2] - t[5]);
-            Ft = (t1 + t2) + t3;
+            Ft = first ? (em + e2) + t3 : (e1 + em) + t3;
         }
+        // lexicographic minimum of (Ft, lane) over the group's 16 lanes (one
+        // DPP row): swaps within pairs and quads, then the mirror images
+        // within each half row and within the row; the order is total, so
+        // every lane ends with the first strict minimum
         double best = Ft;
         int bl = lane;
-#pragma unroll
-        for (int off = 1; off < PH_GROUP; off <<= 1) {
-            const double ob = __shfl_xor(best, off, PH_GROUP);
-            const int ol = __shfl_xor(bl, off, PH_GROUP);
-            if (ob < best || (ob == best && ol < bl)) {
-                best = ob;
-                bl = ol;
-            }
-        }
+        row_min_step<0xB1>(best, bl);   // quad_perm [1, 0, 3, 2]
+        row_min_step<0x4E>(best, bl);   // quad_perm [2, 3, 0, 1]
+        row_min_step<0x141>(best, bl);  // row_half_mirror
+        row_min_step<0x140>(best, bl);  // row_mirror
         if (best < F) {
-            const double w1 = __shfl(t1, bl, PH_GROUP), w2 = __shfl(t2, bl, PH_GROUP), w3 = __shfl(t3, bl, PH_GROUP);
+            // the winner is a trial lane: its moved phase and phase 3
+            const double wm = __shfl(em, bl, PH_GROUP), w3 = __shfl(t3, bl, PH_GROUP);
             const int bk = bl >> 1;
             const double bs = (bl & 1) ? -step : step;
 #pragma unroll
             for (int j = 0; j < 6; ++j)
                 if (j == bk) z[j] += bs;
             F = best;
-            e1 = w1;
-            e2 = w2;
+            if (bk < 3)
+                e1 = wm;
+            else
+                e2 = wm;
             e3 = w3;
         } else {
             step *= 0.5;
