@@ -187,8 +187,9 @@ def copy_gbs(nbytes=1 << 30, reps=20):
 def traffic_from_profiles(schedule: int):
     """HBM bytes per launch of the sweep kernel under `schedule`, measured
     with rocprofv3 FETCH_SIZE / WRITE_SIZE and recorded in profiles/ together
-    with the hash of the sweep source they were taken on; None when the
-    source has changed since or the schedule was not profiled."""
+    with the hash of the sweep source and of the plan code that lays out the
+    state they were taken on; None when either has changed since or the
+    schedule was not profiled."""
     path = os.path.join(ROOT, "profiles", "k_sweep_spinodal2048_f64_traffic.md")
     if not os.path.exists(path):
         return None
@@ -204,7 +205,7 @@ def sweep_source_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for fn in ("sweep.hpp", "schedules.hpp"):
+    for fn in ("sweep.hpp", "schedules.hpp", "api.cpp"):
         h.update(open(os.path.join(ROOT, "paper_1805_07251_amd", "csrc", fn), "rb").read())
     return h.hexdigest()
 
@@ -672,8 +673,9 @@ def _inputs():
 LEGS = {
     # the 64^2 correctness case: L2-resident, so a latency figure, not a roofline one
     "spinodal_64_f64": lambda a: sweep_line(_inputs().spinodal_small(a.seed), "f64", 1000, a.warmup),
-    "spinodal_2048_f32": lambda a: sweep_line(_inputs().spinodal_large(a.seed, dtype="f32"), "f32", a.steps,
-                                              a.warmup),
+    # at least 1,000 steps: the first ~200 steps of a run are a few per cent slower
+    "spinodal_2048_f32": lambda a: sweep_line(_inputs().spinodal_large(a.seed, dtype="f32"), "f32",
+                                              max(a.steps, 1000), a.warmup),
     "mixture4_1024_f32": lambda a: sweep_line(_inputs().mixture4(a.seed), "f32", 5000, a.warmup),
     "batched": lambda a: batch_leg(a.seed, 20000, 10),
     "d1q3_line_16M_f64": lambda a: sweep_line(_inputs().line_spinodal(a.seed, L=1 << 24), "f64", 2000, a.warmup),

@@ -123,8 +123,12 @@ vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out);
 /* Release the plan, its device flag word and its cached graphs (NULL is a no-op). */
 vdwlb_status vdwlb_plan_destroy(vdwlb_plan* plan);
 
-/* Sites per velocity plane of a population buffer (nx*ny rounded up to a
- * multiple of 64); a plane holds plane_elems * C elements. */
+/* Sites per velocity plane of a population buffer: nx*ny rounded up to a
+ * multiple of 64, and for D2Q9 plans whose plane would then span a multiple
+ * of 8 KiB, about 5 KiB more (whole multiples of 64 sites), so that the
+ * planes a sweep streams do not all start at the same phase of the memory
+ * interleave.  Sites from nx*ny on are padding, never read or written.  A
+ * plane holds plane_elems * C elements. */
 int64_t vdwlb_plane_elems(const vdwlb_plan* plan);
 
 /* Bytes of one population buffer: Q * C * plane_elems * sizeof(dtype)

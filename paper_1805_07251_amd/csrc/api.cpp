@@ -39,6 +39,23 @@ namespace vdwlb {
 
 int32_t set_device_error(hipError_t e, const char* where) { return dev_fail(e, where); }
 
+// Sites per velocity plane of a plain plan's state: nx ny rounded up to 64,
+// and for D2Q9, when that leaves the byte stride between planes a multiple
+// of PLANE_ALIAS, about PLANE_PAD_BYTES more (whole multiples of 64 sites).
+// A D2Q9 sweep streams nine planes in and nine out at the same site offsets;
+// with a stride of a large power of two all eighteen streams meet the memory
+// interleave at the same phase.  Measured on 2048^2 with 2 components:
+// FP64 212 -> 208.6-210 us per step, FP32 121.5 -> 113-115 us; 1024^2 with
+// 4 components in FP32 61.5 -> 58.5 us.  The D1Q3 line (three planes each
+// way) gains nothing and keeps the plain stride.
+constexpr int64_t PLANE_ALIAS = 8192, PLANE_PAD_BYTES = 5120;
+int64_t plan_plane(int64_t n, int C, int dtype, int dim) {
+    const int64_t site = (int64_t)C * (dtype == VDWLB_F64 ? 8 : 4);
+    int64_t plane = (n + 63) / 64 * 64;
+    if (dim == 2 && plane * site % PLANE_ALIAS == 0) plane += (PLANE_PAD_BYTES / site + 63) / 64 * 64;
+    return plane;
+}
+
 // Every rule of vdwlb_desc, checked on host data only.
 int32_t validate_desc(const vdwlb_desc* d) {
     if (!d) return VDWLB_E_INVALID_ARG;
@@ -48,7 +65,7 @@ int32_t validate_desc(const vdwlb_desc* d) {
     if (d->dim != 1 && d->dim != 2) return VDWLB_E_INVALID_ARG;
     if (d->dtype != VDWLB_F64 && d->dtype != VDWLB_F32) return VDWLB_E_INVALID_ARG;
     if (C <= VDWLB_MAX_COMPONENTS) {  // kernels address a plane with 32-bit byte offsets
-        const int64_t plane = ((int64_t)d->nx * d->ny + 63) / 64 * 64;
+        const int64_t plane = plan_plane((int64_t)d->nx * d->ny, C, d->dtype, d->dim);
         if (plane * C * (d->dtype == VDWLB_F64 ? 8 : 4) > (int64_t)0xffffffff) return VDWLB_E_INVALID_ARG;
     }
     if (d->force != VDWLB_FORCE_LOG && d->force != VDWLB_FORCE_NID) return VDWLB_E_INVALID_ARG;
@@ -126,6 +143,7 @@ vdwlb_status vdwlb_plan_create(const vdwlb_desc* d, vdwlb_plan** out) {
     if (st != VDWLB_OK) return st;
     vdwlb_plan* p = new (std::nothrow) vdwlb_plan(plan_from_desc(*d));
     if (!p) return VDWLB_E_DEVICE;
+    p->plane = plan_plane((int64_t)d->nx * d->ny, p->C, p->dtype, p->dim);
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_flag, 256);
     if (e == hipSuccess) e = hipMemset(p->d_flag, 0, 256);
