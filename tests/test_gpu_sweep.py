@@ -172,6 +172,24 @@ def test_component_counts(gpu, orc, C, dtype):
     assert rel_err(rho, ref.moments()[0]) <= tol
 
 
+@pytest.mark.parametrize("nx, ny, C, dtype, dim, want", [
+    (2048, 2048, 2, "f64", 2, 2048 * 2048 + 320),  # 64 MiB planes: 5 KiB more
+    (2048, 2048, 2, "f32", 2, 2048 * 2048 + 640),
+    (1024, 1024, 4, "f32", 2, 1024 * 1024 + 320),
+    (256, 256, 3, "f64", 2, 256 * 256 + 256),  # 24-byte sites: 6 KiB, whole multiples of 64 sites
+    (100, 100, 2, "f64", 2, 10048),  # 157 KiB planes: no multiple of 8 KiB, no padding
+    (1 << 16, 1, 2, "f64", 1, 1 << 16),  # D1Q3 lines keep the plain stride
+])
+def test_plane_padding(gpu, nx, ny, C, dtype, dim, want):
+    """A D2Q9 plan whose planes would span a multiple of 8 KiB gets about 5 KiB
+    more per plane; the state's size follows the plane."""
+    a = np.full((C, C), 0.1) + np.eye(C) * 0.1
+    plan = gpu.Plan(nx, ny, 0.3, a, np.full(C, 0.1), np.eye(C) * 0.1, dtype=dtype, dim=dim)
+    assert plan.plane == want
+    q = 9 if dim == 2 else 3
+    assert plan.state_bytes == q * C * want * (8 if dtype == "f64" else 4)
+
+
 def test_nid_force_and_tau(gpu, orc):
     w = I.spinodal_small(3, n=40)
     w.force, w.tau = 1, 0.8
