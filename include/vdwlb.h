@@ -53,7 +53,9 @@
 extern "C" {
 #endif
 
-#define VDWLB_ABI_VERSION 1
+/* 2: D2Q9 velocity planes may be padded beyond nx*ny rounded up to 64
+ * (vdwlb_plane_elems). */
+#define VDWLB_ABI_VERSION 2
 #define VDWLB_MAX_COMPONENTS 4
 
 typedef int32_t vdwlb_status;

@@ -12,6 +12,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvdwlb.so")
+ABI_VERSION = 2  # VDWLB_ABI_VERSION of include/vdwlb.h
 
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_DEVICE, E_UNPHYSICAL, E_CAPACITY = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
@@ -95,6 +96,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.vdwlb_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.vdwlb_abi_version()}, this binding expects "
+                               f"{ABI_VERSION}: rebuild it with `python -m paper_1805_07251_amd.build`")
         _lib = L
     return _lib
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version_and_strerror():
-    assert V.lib().vdwlb_abi_version() == 1
+    assert V.lib().vdwlb_abi_version() == V.ABI_VERSION == 2
     for s in range(5):
         assert V.lib().vdwlb_strerror(s)
 
