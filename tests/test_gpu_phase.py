@@ -157,6 +157,23 @@ def test_points_independent_of_batch(phase):
         assert full[k][::3].tobytes() == sub[k].tobytes(), k
 
 
+def test_iteration_cap_inside_a_later_pass(phase):
+    """A cap of 25,000 iterations per search falls inside the second pass
+    (the first ends at 20,000): points whose searches all stay below it give
+    the default cap's outputs bit for bit, and no point runs more than one cap
+    per search (three searches at most)."""
+    a, b = baseline()
+    NA, NB = phase.composition_grid(b, 28)
+    full = host(phase.phase_points(KT, a, b, NA, NB))
+    cap = host(phase.phase_points(KT, a, b, NA, NB, max_iter=25000))
+    assert np.all(cap["iterations"] <= 3 * 25000)
+    below = full["iterations"] < 25000  # then every search of the point stayed below the cap
+    assert below.sum() >= 50 and (~below).sum() >= 5
+    for k in ("phases", "raw", "F", "status", "iterations", "n_unstable", "polished"):
+        assert full[k][below].tobytes() == cap[k][below].tobytes(), k
+    assert np.all(cap["iterations"][~below] >= 25000)
+
+
 def test_iteration_cap_and_invalid_points(phase):
     """max_iter = 1 stops every search (and restart) after one iteration and still returns
     a classified result; invalid compositions give status -1 and no phases;
