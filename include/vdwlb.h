@@ -237,7 +237,7 @@ vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, doubl
  *     iterations > 0 means the search did not split), 0 if the search ended
  *     with an infinite free energy.
  *   kT, a (host, 2 x 2 row-major, symmetric), b (host, 2): the mixture of Sec. II.
- *   n >= 0; NA, NB: device [n] doubles, read.
+ *   0 <= n <= 2^31 - 257; NA, NB: device [n] doubles, read.
  *   threshold > 0 (the paper uses 1e-12); 1 <= max_iter <= 7e8 iterations
  *   per search.
  *   phases  device [n][3][3] (rho_A, rho_B, V) of the distinct phases, unused
@@ -256,7 +256,7 @@ vdwlb_status vdwlb_maxwell(double a, double b, double kT, double* rho_gas, doubl
  * takes a stream-ordered workspace of 4 (64 + 2 n) bytes (hipMallocAsync on
  * stream, freed on stream after the last kernel).
  * VDWLB_E_INVALID_ARG for kT or threshold not positive and finite, a not finite
- * or not symmetric, b not positive, n < 0, max_iter < 1, or a NULL pointer when
+ * or not symmetric, b not positive, n out of range, max_iter < 1, or a NULL pointer when
  * n > 0; a device error if the workspace cannot be allocated.  Asynchronous on
  * stream. */
 vdwlb_status vdwlb_phase_points(double kT, const double* a, const double* b, int32_t n, const double* NA,

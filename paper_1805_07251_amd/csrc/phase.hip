@@ -547,7 +547,7 @@ k_phase_search(Mix m, int n, const double* __restrict__ NA, const double* __rest
                int* __restrict__ list_out, int* __restrict__ count_out, double* __restrict__ state,
                double* __restrict__ raw, double* __restrict__ Fout, int* __restrict__ info) {
     const int lane = threadIdx.x & (PH_GROUP - 1);
-    const int slot = (int)((blockIdx.x * blockDim.x + threadIdx.x) / PH_GROUP);
+    const int slot = (int)(blockIdx.x * (blockDim.x / PH_GROUP) + threadIdx.x / PH_GROUP);  // below n + 16
     int i = slot;
     if (list_in) {
         if (slot >= *count_in) return;  // whole groups leave together
@@ -733,7 +733,7 @@ using namespace vdwlb;
 extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const double* b, int32_t n, const double* NA,
                                            const double* NB, double threshold, int32_t max_iter, double* phases,
                                            double* raw, double* F, int32_t* info, void* stream) {
-    if (!a || !b || n < 0) return VDWLB_E_INVALID_ARG;
+    if (!a || !b || n < 0 || n > INT_MAX - 256) return VDWLB_E_INVALID_ARG;  // thread indices stay in int
     if (!(kT > 0.0) || !finite_host(kT) || !(threshold > 0.0) || !finite_host(threshold) || max_iter < 1 ||
         max_iter > PH_MAX_ITER)
         return VDWLB_E_INVALID_ARG;
@@ -745,7 +745,7 @@ extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const dou
     if (n == 0) return VDWLB_OK;
     if (!NA || !NB || !phases || !raw || !F || !info) return VDWLB_E_INVALID_ARG;
     const Mix m{kT, a[0], a[1], a[3], b[0], b[1]};
-    const unsigned nb = (unsigned)((n + PH_BLOCK - 1) / PH_BLOCK);
+    const unsigned nb = (unsigned)(((int64_t)n + PH_BLOCK - 1) / PH_BLOCK);
     const hipStream_t s = (hipStream_t)stream;
     // stream-ordered workspace: one counter per pass, then two work lists of n
     // points (ping-pong between passes); the search state of a point that
@@ -761,7 +761,7 @@ extern "C" vdwlb_status vdwlb_phase_points(double kT, const double* a, const dou
     for (int p = 0; p <= PH_PASSES && e == hipSuccess; ++p) {
         const bool last = p == PH_PASSES;
         const int block = p < PH_WIDE_FROM ? PH_BLOCK : PH_WIDE, points = block / PH_GROUP;
-        const unsigned nbs = (unsigned)((n + points - 1) / points);
+        const unsigned nbs = (unsigned)(((int64_t)n + points - 1) / points);
         hipLaunchKernelGGL(k_phase_search, dim3(nbs), dim3(block), 0, s, m, (int)n, NA, NB, threshold,
                            (int)max_iter, last ? INT_MAX : PH_PASS_ITERS[p],
                            p == 0 ? (const int*)nullptr : (const int*)list[(p - 1) & 1],

@@ -143,6 +143,7 @@ def test_phase_points_validates_on_the_host():
     assert call(thr=0.0) == V.E_INVALID_ARG
     assert call(it=0) == V.E_INVALID_ARG
     assert call(n=-1) == V.E_INVALID_ARG
+    assert call(n=2**31 - 256) == V.E_INVALID_ARG  # thread indices of the kernels stay in int32
     assert call(a=np.array([0.45, 0.2, 0.225, 0.45])) == V.E_INVALID_ARG
     assert call(a=np.array([0.45, np.inf, np.inf, 0.45])) == V.E_INVALID_ARG
     assert call(b=np.array([1 / 3, 0.0])) == V.E_INVALID_ARG
